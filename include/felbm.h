@@ -1,0 +1,193 @@
+/*
+ * felbm.h - C ABI of the MI355X finite-element lattice Boltzmann library for
+ * binary fluids (Lee-Lin free-energy model with characteristic-Galerkin
+ * streaming and local collision/forcing; Matin et al., arXiv 1608.01906).
+ *
+ * One context advances one or more independent meshes ("instances") on one
+ * GPU.  Per time step (Section 2.2, pre-streaming / streaming /
+ * post-streaming split) the library runs, for every instance and every
+ * population of both distributions (f: order parameter = density,
+ * g: pressure-momentum):
+ *   1. streaming right-hand side  -(dt C_a + dt^2 D_a) psi_a   (Section 2.2.1)
+ *   2. the mass-matrix solve M Delta_a = rhs_a by lumped-preconditioned
+ *      conjugate gradients with a fixed iteration count (or the lumped-mass
+ *      approximation of Section 2.2.1)
+ *   3. walls (nodal bounce-back) and the density moment (Section 2.2)
+ *   4. nodal derivatives by volume-weighted recovery (Section 2.3)
+ *   5. one fused post-streaming + pre-streaming collision with the
+ *      potential-form force F, stress-form force G and exact-difference
+ *      body force (Sections 2.1, 2.2)
+ *
+ * Conventions for every call:
+ *  - All arrays passed in or out are HOST arrays in the caller's node order;
+ *    the library copies them.  Vector fields are [n_nodes][dim], row-major.
+ *    Populations are [2Q][n_nodes]: f_0..f_{Q-1} then g_0..g_{Q-1}, in the
+ *    velocity order documented under FEL_LATTICE_*.
+ *  - Device memory is one caller-owned buffer handed over by fel_bind (e.g.
+ *    a PyTorch uint8 tensor); the library sub-allocates it and never frees
+ *    it.  The library never calls hipMalloc for state.  The caller's stream
+ *    orders all device work.
+ *  - Every function returns a fel_status; on failure fel_last_error gives a
+ *    message.  No exception or abort crosses the ABI.  fel_step is
+ *    asynchronous: device-side conditions (non-finite values, CG residual
+ *    above tolerance) surface at the next fel_sync / read call.
+ *  - A context is not thread-safe.
+ */
+#ifndef FELBM_H
+#define FELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEL_API __attribute__((visibility("default")))
+
+typedef struct fel_ctx fel_ctx;
+
+typedef enum {
+    FEL_OK = 0,
+    FEL_EINVAL = -1,      /* bad argument, bad mesh (inverted element, index out of range) */
+    FEL_ENOMEM = -2,      /* host allocation failed or bound workspace too small */
+    FEL_EDEVICE = -3,     /* a HIP runtime call failed */
+    FEL_ESTATE = -4,      /* call out of order (e.g. step before bind / init) */
+    FEL_ENOTCONV = -5,    /* a CG solve ended above the residual tolerance (state still advanced) */
+    FEL_ENONFINITE = -6   /* a non-finite population or field was produced */
+} fel_status;
+
+/* Lattices (Section 2.1 uses D3Q19; 2-D meshes use D2Q9).
+ * D2Q9 order:  0 (0,0); 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1); 5 (1,1); 6 (-1,1); 7 (-1,-1); 8 (1,-1).
+ * D3Q19 order: 0 rest; 1..6 (+-x, +-y, +-z as +x,-x,+y,-y,+z,-z);
+ *              7..10 (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0); 11..14 (1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1);
+ *              15..18 (0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1).  Weights are the standard ones. */
+#define FEL_LATTICE_D2Q9 9
+#define FEL_LATTICE_D3Q19 19
+
+#define FEL_PREC_FP64 0        /* everything in FP64 */
+#define FEL_PREC_FP32 1        /* FP32 operators, vectors and collision; populations stored as FP32
+                                  scaled deviations from w_a * a node reference; FP64 CG dots and sums */
+#define FEL_PREC_FP32_FP16 2   /* as FP32 but the stored deviations are FP16 */
+
+#define FEL_MASS_CONSISTENT 0  /* solve with the consistent mass matrix (conjugate gradients) */
+#define FEL_MASS_LUMPED 1      /* lumped-mass approximation (end of Section 2.2.1) */
+
+#define FEL_LAP_NESTED 0       /* Laplacian = recovered divergence of the recovered gradient */
+#define FEL_LAP_WEAK 1         /* Laplacian = -m^-1 (sum_r K_rr) rho (Galerkin, lumped mass) */
+
+typedef struct {
+    int lattice;          /* FEL_LATTICE_D2Q9 or FEL_LATTICE_D3Q19 */
+    int precision;        /* FEL_PREC_* */
+    int mass_mode;        /* FEL_MASS_* */
+    int cg_iters;         /* CG iterations per solve; 0 = default (2-D: 30 FP64 / 15 FP32; 3-D: 34 / 17) */
+    double cg_tol;        /* after the last iteration, sqrt(r.z / r0.z0) above this flags FEL_ENOTCONV;
+                             0 = default (1e-11 FP64, 1e-5 FP32) */
+    int laplacian_mode;   /* FEL_LAP_* */
+    int max_instances;    /* number of independent meshes this context may hold (>= 1) */
+} fel_options;
+
+/* Physical parameters of one instance (Section 2.1).  rho_l is the heavy
+ * (liquid) bulk density, rho_v the light (vapour) one, rho_l > rho_v > 0.
+ * tau_* are the dimensionless bulk relaxation times (kinematic viscosity
+ * cs^2 tau dt), combined by the composition-weighted harmonic mean.  sigma
+ * and xi give beta = 12 sigma / (xi (rho_l - rho_v)^4) and
+ * kappa = 3 xi sigma / (2 (rho_l - rho_v)^2).  grav is the body
+ * acceleration (components beyond dim are ignored). */
+typedef struct {
+    double rho_l, rho_v, tau_l, tau_v, sigma, xi, dt, grav[3];
+} fel_phys;
+
+/* Creates a context.  Validates the options; allocates host memory only. */
+FEL_API fel_status fel_create(const fel_options* opt, fel_ctx** out);
+
+/* Uploads the P1 simplex mesh of instance `inst` (0 <= inst < max_instances)
+ * and assembles its operators on the host (Section 2.2.1, finite-element
+ * matrices; Section 2.3, recovery).  Must precede fel_workspace_size/bind.
+ *   dim         2 (triangles, D2Q9) or 3 (tetrahedra, D3Q19)
+ *   xyz         [n_nodes][dim] node coordinates
+ *   conn        [n_elems][dim+1] vertex indices (0-based), positively oriented
+ *   shift       [n_elems][dim+1][dim] periodic image of each vertex (unwrapped
+ *               position = xyz + shift * box), or NULL for none
+ *   box         [dim] period per axis (0 = not periodic), may be NULL if shift is NULL
+ *   wall        [n_nodes] 1 on no-slip wall nodes, or NULL
+ *   wall_normal [n_nodes][dim] unit normal into the fluid at wall nodes, or NULL
+ * Errors: FEL_EINVAL on a bad index, a non-positive element volume, a
+ * dimension that does not match the lattice, or a re-upload after fel_bind. */
+FEL_API fel_status fel_upload_mesh(fel_ctx* ctx, int inst, int dim, int64_t n_nodes, const double* xyz,
+                                   int64_t n_elems, const int32_t* conn, const int8_t* shift,
+                                   const double* box, const uint8_t* wall, const double* wall_normal);
+
+/* Device bytes needed for every uploaded instance (call after all uploads). */
+FEL_API fel_status fel_workspace_size(fel_ctx* ctx, size_t* bytes);
+
+/* Binds a caller-owned device buffer of at least fel_workspace_size bytes
+ * (256-byte aligned) and the HIP stream (hipStream_t, NULL = default
+ * stream) all work is ordered on; copies the operators to the device. */
+FEL_API fel_status fel_bind(fel_ctx* ctx, void* dev_ptr, size_t bytes, void* hip_stream);
+
+/* Sets the physics of `inst` and initialises its populations to the
+ * equilibrium of the given nodal density rho [n], velocity u [n][dim] and
+ * pressure p [n], plus the forcing of a pre-streaming collision (whose BGK
+ * part vanishes at equilibrium).  u or p may be NULL for zero. */
+FEL_API fel_status fel_init_fields(fel_ctx* ctx, int inst, const fel_phys* phys, const double* rho,
+                                   const double* u, const double* p);
+
+/* Advances every instance by n_steps time steps; asynchronous on the bound stream. */
+FEL_API fel_status fel_step(fel_ctx* ctx, int n_steps);
+
+/* Waits for the stream and reports device conditions raised since the last
+ * sync: FEL_ENONFINITE, then FEL_ENOTCONV; clears them. */
+FEL_API fel_status fel_sync(fel_ctx* ctx);
+
+/* Fields of the last step of `inst` (or of its initial state): density,
+ * velocity [n][dim], pressure and composition C = (rho - rho_v)/(rho_l - rho_v).
+ * Any pointer may be NULL.  Synchronises the stream. */
+FEL_API fel_status fel_read_fields(fel_ctx* ctx, int inst, double* rho, double* u, double* p, double* C);
+
+/* Per-instance FP64 sums over nodes with the lumped mass m as weight:
+ * out[0] = sum m rho, out[1] = sum m C, out[2] = sum m (1 - C),
+ * out[3..5] = sum m sum_a e_a gbar_a (zero beyond dim), from the stored
+ * pre-streaming populations.  Synchronises the stream. */
+FEL_API fel_status fel_conserved_sums(fel_ctx* ctx, int inst, double out[6]);
+
+/* Checkpoint / restart: the stored pre-streaming populations of `inst` as
+ * [2Q][n_nodes] FP64 (FP32 modes convert).  fel_set_state needs the
+ * physics set by a prior fel_init_fields. */
+FEL_API fel_status fel_get_state(fel_ctx* ctx, int inst, double* psibar);
+FEL_API fel_status fel_set_state(fel_ctx* ctx, int inst, const double* psibar);
+
+/* Diagnostics of the last step of `inst`, in FP64, caller node order:
+ * FEL_AUX_GRADRHO [n][dim] recovered density gradient; FEL_AUX_MU [n]
+ * chemical potential mu_phi - kappa lap rho; FEL_AUX_S [n][dim] stress
+ * vector kappa [d_i |grad rho|^2 - d_j (d_i rho d_j rho)]; FEL_AUX_DELTA
+ * [2Q][n] streaming increments (rest direction zero). */
+#define FEL_AUX_GRADRHO 0
+#define FEL_AUX_MU 1
+#define FEL_AUX_S 2
+#define FEL_AUX_DELTA 3
+FEL_API fel_status fel_read_aux(fel_ctx* ctx, int inst, int which, double* out);
+
+/* Kernel timing with HIP events on the bound stream, for roofline
+ * measurement.  fel_profile(ctx, 1) starts recording an event pair around
+ * every kernel launch of fel_step (graph replay is disabled meanwhile);
+ * fel_profile_read returns, per kernel class k < n_classes, the launch count
+ * and the summed duration in ms, and the class names; fel_profile(ctx, 0)
+ * stops and clears. */
+FEL_API fel_status fel_profile(fel_ctx* ctx, int enable);
+FEL_API fel_status fel_profile_read(fel_ctx* ctx, int max_classes, int* n_classes, int64_t* counts,
+                                    double* total_ms, const char** names);
+
+/* Sizes of the device layout (for traffic accounting): total padded rows,
+ * ELL width, number of stored populations and CG iterations per step. */
+FEL_API fel_status fel_layout_info(fel_ctx* ctx, int64_t* rows, int* ell_width, int* pops, int* cg_iters);
+
+FEL_API fel_status fel_destroy(fel_ctx* ctx);
+FEL_API const char* fel_last_error(const fel_ctx* ctx);
+FEL_API const char* fel_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FELBM_H */

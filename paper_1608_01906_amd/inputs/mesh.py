@@ -1,0 +1,152 @@
+"""Seeded synthetic P1 meshes (inputs shared by the oracle and the device path).
+
+The paper samples the populations at the vertices of a linear simplex mesh
+(Section 2.2.1, discrete-field equation) but gives its meshes only by element
+count (Section 3.1, Table 1), so every workload here runs on a generated
+stand-in: a unit-spaced grid whose nodes are jittered uniformly, each square
+cell cut into 2 triangles along its (0,0)-(1,1) diagonal, each cube cell cut
+into the 6 Kuhn tetrahedra around its (0,0,0)-(1,1,1) diagonal.
+
+This module holds no arithmetic of the method: it only places nodes, lists
+elements and flags wall nodes.  Random numbers come from SplitMix64
+(Steele, Lea and Flood, OOPSLA 2014), evaluated counter-style so that the
+i-th draw of a stream is mix(seed + (i+1) * 0x9E3779B97F4A7C15).
+
+Mesh dictionary (all numpy arrays, caller node order):
+  dim        2 or 3
+  xyz        float64 [n_nodes, dim]   node coordinates (inside or near the box)
+  conn       int32   [n_elems, dim+1] vertex indices, positively oriented
+  shift      int8    [n_elems, dim+1, dim] periodic image of each vertex:
+             unwrapped position = xyz[conn[e, a]] + shift[e, a] * box
+  box        float64 [dim]  period along each axis, 0 where the axis is walled
+  wall       uint8   [n_nodes] 1 on wall nodes
+  wall_normal float64 [n_nodes, dim] unit normal pointing into the fluid
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, n: int, start: int = 0) -> np.ndarray:
+    """Draws start..start+n-1 of the SplitMix64 stream seeded with `seed`."""
+    with np.errstate(over="ignore"):
+        i = np.arange(start + 1, start + n + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + i * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def uniform01(seed: int, n: int, start: int = 0) -> np.ndarray:
+    """Uniform doubles in [0, 1) from the top 53 bits of each draw."""
+    return (splitmix64(seed, n, start) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def _jitter(seed: int, n_nodes: int, dim: int, amp: float) -> np.ndarray:
+    if amp == 0.0:
+        return np.zeros((n_nodes, dim))
+    u = uniform01(seed, n_nodes * dim).reshape(n_nodes, dim)
+    return (2.0 * u - 1.0) * amp
+
+
+def grid_mesh_2d(nx: int, ny: int, *, wall_y: bool = False, jitter: float = 0.2,
+                 seed: int = 1608) -> dict:
+    """nx x ny node grid, periodic in x; periodic in y unless `wall_y`.
+
+    With walls the node rows j = 0 and j = ny-1 lie on the walls (y exact,
+    jittered along x only) and there are ny-1 cell rows; otherwise ny cell
+    rows wrap around.
+    """
+    if nx < 2 or ny < 2:
+        raise ValueError("grid needs at least 2 nodes per axis")
+    n = nx * ny
+    j_idx, i_idx = np.divmod(np.arange(n, dtype=np.int64), nx)
+    xyz = np.stack([i_idx, j_idx], axis=1).astype(np.float64)
+    jit = _jitter(seed, n, 2, jitter)
+    wall = np.zeros(n, np.uint8)
+    normal = np.zeros((n, 2))
+    if wall_y:
+        on_wall = (j_idx == 0) | (j_idx == ny - 1)
+        jit[on_wall, 1] = 0.0
+        wall[on_wall] = 1
+        normal[j_idx == 0, 1] = 1.0
+        normal[j_idx == ny - 1, 1] = -1.0
+    xyz += jit
+    box = np.array([float(nx), 0.0 if wall_y else float(ny)])
+
+    ncy = ny - 1 if wall_y else ny
+    cj, ci = np.divmod(np.arange(nx * ncy, dtype=np.int64), nx)
+
+    def corner(di, dj):
+        ii, jj = ci + di, cj + dj
+        sx, sy = ii // nx, jj // ny
+        node = (jj % ny) * nx + (ii % nx)
+        return node, np.stack([sx, sy], axis=1)
+
+    c00, s00 = corner(0, 0)
+    c10, s10 = corner(1, 0)
+    c11, s11 = corner(1, 1)
+    c01, s01 = corner(0, 1)
+    conn = np.empty((2 * nx * ncy, 3), np.int32)
+    shift = np.empty((2 * nx * ncy, 3, 2), np.int8)
+    conn[0::2] = np.stack([c00, c10, c11], axis=1)
+    conn[1::2] = np.stack([c00, c11, c01], axis=1)
+    shift[0::2] = np.stack([s00, s10, s11], axis=1)
+    shift[1::2] = np.stack([s00, s11, s01], axis=1)
+    return dict(dim=2, xyz=xyz, conn=conn, shift=shift, box=box, wall=wall,
+                wall_normal=normal)
+
+
+def _kuhn_corners():
+    """The 6 Kuhn tetrahedra of the unit cube as corner offsets, oriented positively."""
+    tets = []
+    for perm in itertools.permutations(range(3)):
+        v = [np.zeros(3, np.int64)]
+        for ax in perm:
+            nxt = v[-1].copy()
+            nxt[ax] = 1
+            v.append(nxt)
+        det = np.linalg.det(np.array([v[1] - v[0], v[2] - v[0], v[3] - v[0]], float))
+        if det < 0:
+            v[1], v[2] = v[2], v[1]
+        tets.append(v)
+    return tets
+
+
+def grid_mesh_3d(nx: int, ny: int, nz: int, *, jitter: float = 0.2, seed: int = 1608) -> dict:
+    """nx x ny x nz periodic node grid cut into Kuhn tetrahedra."""
+    if min(nx, ny, nz) < 2:
+        raise ValueError("grid needs at least 2 nodes per axis")
+    n = nx * ny * nz
+    idx = np.arange(n, dtype=np.int64)
+    k_idx, rem = np.divmod(idx, nx * ny)
+    j_idx, i_idx = np.divmod(rem, nx)
+    xyz = np.stack([i_idx, j_idx, k_idx], axis=1).astype(np.float64)
+    xyz += _jitter(seed, n, 3, jitter)
+    box = np.array([float(nx), float(ny), float(nz)])
+    dims = np.array([nx, ny, nz])
+    cells = np.stack([i_idx, j_idx, k_idx], axis=1)  # one cell per node (periodic)
+
+    conn = np.empty((6 * n, 4), np.int32)
+    shift = np.empty((6 * n, 4, 3), np.int8)
+    for t, corners in enumerate(_kuhn_corners()):
+        for a, off in enumerate(corners):
+            p = cells + off
+            s = p // dims
+            q = p % dims
+            conn[t::6, a] = (q[:, 2] * ny + q[:, 1]) * nx + q[:, 0]
+            shift[t::6, a] = s
+    return dict(dim=3, xyz=xyz, conn=conn, shift=shift, box=box,
+                wall=np.zeros(n, np.uint8), wall_normal=np.zeros((n, 3)))
+
+
+def mesh_summary(mesh: dict) -> dict:
+    return dict(dim=mesh["dim"], n_nodes=int(mesh["xyz"].shape[0]),
+                n_elems=int(mesh["conn"].shape[0]),
+                n_wall=int(mesh["wall"].sum()))

@@ -1,0 +1,232 @@
+"""Seeded synthetic workloads: mesh, physical parameters and initial fields.
+
+The paper's benchmarks (Section 3) use meshes and data that are not
+published, so each workload here is a generated stand-in with the same
+geometry class, parameter ranges and structure:
+
+  droplet2d   periodic square, circular drop at rest (Section 3.1, in 2-D)
+  channel2d   layered two-phase planar Poiseuille flow between walls
+              (2-D analogue of the concurrent pipe flow of Section 3.3)
+  rt2d        Rayleigh-Taylor: heavy over light between walls, cosine
+              perturbation of the interface (2-D analogue of Section 3.4)
+  droplet3d   periodic cube, spherical drop at rest (Section 3.1)
+  ensemble2d  many independent periodic droplets of uneven size
+
+Initial fields are the caller's: density rho, velocity u and pressure p at
+the nodes.  Phase labels follow the chemical-potential definition of
+Section 2.1: rho_l is the heavy (liquid) phase and rho_v the light one.
+The time step is 0.25 on unit-spaced meshes for every workload: at 1 the
+characteristic-Galerkin streaming is unstable on these meshes, while 0.25
+keeps the dimensionless relaxation time tau (lambda / dt) as stated.
+
+None of the method's arithmetic is here: the density profiles are the flat
+tanh interface of width xi, and the channel velocity is the quadrature of
+the steady Stokes equation for the given viscosity profile.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .mesh import grid_mesh_2d, grid_mesh_3d, uniform01
+
+DT_RUN = 0.25
+CS2 = 1.0 / 3.0
+
+
+@dataclass
+class Phys:
+    rho_l: float          # heavy / liquid bulk density
+    rho_v: float          # light / vapour bulk density
+    tau_l: float          # dimensionless relaxation time of the heavy phase
+    tau_v: float          # ... of the light phase
+    sigma: float          # surface tension
+    xi: float             # interface width
+    dt: float = DT_RUN
+    grav: tuple = (0.0, 0.0, 0.0)
+
+    def as_tuple(self):
+        g = tuple(self.grav) + (0.0,) * (3 - len(self.grav))
+        return (self.rho_l, self.rho_v, self.tau_l, self.tau_v, self.sigma, self.xi, self.dt) + g[:3]
+
+
+@dataclass
+class Instance:
+    mesh: dict
+    phys: Phys
+    rho0: np.ndarray
+    u0: np.ndarray
+    p0: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+
+@dataclass
+class Workload:
+    name: str
+    lattice: int                  # 9 (D2Q9) or 19 (D3Q19)
+    instances: list
+    steps: int
+    description: str = ""
+
+    @property
+    def n_nodes(self) -> int:
+        return int(sum(i.mesh["xyz"].shape[0] for i in self.instances))
+
+
+def _tanh_profile(signed_dist, rho_l, rho_v, xi):
+    """Flat-interface density: heavy where signed_dist > 0."""
+    return 0.5 * (rho_l + rho_v) + 0.5 * (rho_l - rho_v) * np.tanh(2.0 * signed_dist / xi)
+
+
+def _min_image(d, L):
+    if L > 0:
+        d = d - L * np.round(d / L)
+    return d
+
+
+def droplet_instance(mesh, *, radius, rho_l, rho_v, sigma, xi, tau_l, tau_v, center=None,
+                     dt=DT_RUN, u0=None) -> Instance:
+    dim = mesh["dim"]
+    box = mesh["box"]
+    if center is None:
+        center = box / 2.0
+    d = np.stack([_min_image(mesh["xyz"][:, a] - center[a], box[a]) for a in range(dim)], axis=1)
+    r = np.sqrt((d ** 2).sum(axis=1))
+    rho = _tanh_profile(radius - r, rho_l, rho_v, xi)
+    comp = (rho - rho_v) / (rho_l - rho_v)
+    dp = (sigma / radius) * (dim - 1)          # Laplace jump: sigma/R in 2-D, 2 sigma/R in 3-D
+    p = dp * comp
+    u = np.zeros((mesh["xyz"].shape[0], dim))
+    if u0 is not None:
+        u[:] = np.asarray(u0, float)[:dim]
+    phys = Phys(rho_l, rho_v, tau_l, tau_v, sigma, xi, dt)
+    return Instance(mesh, phys, rho, u, p,
+                    meta=dict(kind="droplet", radius=radius, center=np.asarray(center, float),
+                              dp_laplace=dp))
+
+
+def droplet2d(n=64, *, jitter=0.2, seed=1608, radius=None, rho_l=1.0, rho_v=0.1, sigma=0.01,
+              xi=4.0, tau=0.05, steps=200) -> Workload:
+    """Static drop in a periodic square (radius n/4 by default)."""
+    mesh = grid_mesh_2d(n, n, jitter=jitter, seed=seed)
+    inst = droplet_instance(mesh, radius=radius if radius is not None else n / 4.0,
+                            rho_l=rho_l, rho_v=rho_v, sigma=sigma, xi=xi, tau_l=tau, tau_v=tau,
+                            center=np.array([n / 2.0, n / 2.0]))
+    return Workload(f"droplet2d_{n}x{n}", 9, [inst], steps,
+                    "D2Q9 static droplet, periodic jittered P1 mesh")
+
+
+def droplet3d(n=128, *, jitter=0.2, seed=1611, radius=None, rho_l=1.0, rho_v=0.01, sigma=0.005,
+              xi=4.0, tau=0.05, steps=500) -> Workload:
+    mesh = grid_mesh_3d(n, n, n, jitter=jitter, seed=seed)
+    inst = droplet_instance(mesh, radius=radius if radius is not None else n / 4.0,
+                            rho_l=rho_l, rho_v=rho_v, sigma=sigma, xi=xi, tau_l=tau, tau_v=tau,
+                            center=np.full(3, n / 2.0))
+    return Workload(f"droplet3d_{n}^3", 19, [inst], steps,
+                    "D3Q19 static droplet, periodic jittered Kuhn-tet mesh")
+
+
+def channel_profile(y, *, half_width, core, rho_heavy, rho_light, tau_heavy, tau_light, xi, g, dt,
+                    sub=64):
+    """Steady layered channel flow for a diffuse interface.
+
+    y is measured from the channel centre; walls at |y| = half_width, light
+    core |y| < core.  Solves d/dy(mu du/dy) = -rho g with u = 0 at the walls
+    and du/dy = 0 at the centre: u(y) = int_|y|^L (int_0^s rho g) / mu(s) ds,
+    with mu = rho cs^2 tau dt and 1/tau the composition-weighted harmonic
+    mean of the bulk values.
+    """
+    L = half_width
+    s = np.linspace(0.0, L, int(np.ceil(L * sub)) + 1)
+    rho = _tanh_profile(np.abs(s) - core, rho_heavy, rho_light, xi)
+    comp = np.clip((rho - rho_light) / (rho_heavy - rho_light), 0.0, 1.0)
+    tau = 1.0 / (comp / tau_heavy + (1.0 - comp) / tau_light)
+    mu = rho * CS2 * tau * dt
+    ds = s[1] - s[0]
+    inner = np.concatenate([[0.0], np.cumsum(0.5 * (rho[1:] + rho[:-1]) * g * ds)])
+    integrand = inner / mu
+    outer = np.concatenate([[0.0], np.cumsum(0.5 * (integrand[1:] + integrand[:-1]) * ds)])
+    u_of_s = outer[-1] - outer                   # int_s^L
+    return np.interp(np.abs(y), s, u_of_s)
+
+
+def channel2d(nx=1024, ny=256, *, jitter=0.2, seed=1609, rho_heavy=1.0, rho_light=1e-3,
+              tau_heavy=0.05, tau_light=1.0, sigma=0.01, xi=4.0, g=1e-7, steps=5000) -> Workload:
+    """Layered Poiseuille flow: heavy fluid along both walls, light core.
+
+    Walls are the node rows y = 0 and y = ny-1; flow along periodic x.
+    """
+    mesh = grid_mesh_2d(nx, ny, wall_y=True, jitter=jitter, seed=seed)
+    yc = 0.5 * (ny - 1)
+    L = 0.5 * (ny - 1)
+    core = 0.25 * (ny - 1)
+    y = mesh["xyz"][:, 1] - yc
+    rho = _tanh_profile(np.abs(y) - core, rho_heavy, rho_light, xi)
+    u = np.zeros((mesh["xyz"].shape[0], 2))
+    u[:, 0] = channel_profile(y, half_width=L, core=core, rho_heavy=rho_heavy, rho_light=rho_light,
+                              tau_heavy=tau_heavy, tau_light=tau_light, xi=xi, g=g, dt=DT_RUN)
+    p = np.zeros(mesh["xyz"].shape[0])
+    phys = Phys(rho_heavy, rho_light, tau_heavy, tau_light, sigma, xi, DT_RUN, (g, 0.0, 0.0))
+    inst = Instance(mesh, phys, rho, u, p,
+                    meta=dict(kind="channel", half_width=L, core=core, yc=yc, g=g))
+    return Workload(f"channel2d_{nx}x{ny}", 9, [inst], steps,
+                    "D2Q9 layered two-phase Poiseuille channel between bounce-back walls")
+
+
+def rt2d(nx=1024, ny=4096, *, jitter=0.2, seed=1610, rho_heavy=1.0, rho_light=1.0 / 3.0,
+         tau=0.05, xi=4.0, g=1e-5, amp=0.1, steps=2000) -> Workload:
+    """Rayleigh-Taylor: heavy on top, light below, walls at y = 0 and y = ny-1."""
+    mesh = grid_mesh_2d(nx, ny, wall_y=True, jitter=jitter, seed=seed)
+    x, y = mesh["xyz"][:, 0], mesh["xyz"][:, 1]
+    H = ny - 1.0
+    yi = 0.5 * H + amp * nx * np.cos(2.0 * np.pi * x / nx)
+    rho = _tanh_profile(y - yi, rho_heavy, rho_light, xi)
+    # hydrostatic pressure of the unperturbed column, p(H) = 0: dp/dy = -rho g
+    ys = np.linspace(0.0, H, int(H) * 8 + 1)
+    rs = _tanh_profile(ys - 0.5 * H, rho_heavy, rho_light, xi)
+    col = np.concatenate([[0.0], np.cumsum(0.5 * (rs[1:] + rs[:-1]) * (ys[1] - ys[0]))])
+    p = g * np.interp(y, ys, col[-1] - col)
+    u = np.zeros((x.size, 2))
+    phys = Phys(rho_heavy, rho_light, tau, tau, 0.0, xi, DT_RUN, (0.0, -g, 0.0))
+    inst = Instance(mesh, phys, rho, u, p, meta=dict(kind="rt", atwood=(rho_heavy - rho_light) /
+                                                      (rho_heavy + rho_light)))
+    return Workload(f"rt2d_{nx}x{ny}", 9, [inst], steps,
+                    "D2Q9 Rayleigh-Taylor, heavy over light, walls top and bottom")
+
+
+def ensemble2d(count=64, *, side_lo=32, side_hi=512, seed=16085, jitter=0.2, sigma=0.01, xi=4.0,
+               tau=0.05, steps=1000, ratio_hi=1000.0, ratio_min=1.05) -> Workload:
+    """Independent periodic droplets with sides ~ U{lo..hi}, density ratio log-uniform.
+
+    Ratios below ratio_min are redrawn from the continuation of the stream
+    (the free-energy coefficients scale with (rho_l - rho_v)^-4 and become
+    stiff as the ratio tends to 1).
+    """
+    u = uniform01(seed, count)
+    sides = side_lo + np.floor(u * (side_hi - side_lo + 1)).astype(int)
+    ratios = []
+    pos = count
+    while len(ratios) < count:
+        r = ratio_hi ** uniform01(seed, 1, pos)[0]
+        pos += 1
+        if r >= ratio_min:
+            ratios.append(r)
+    insts = []
+    for i, (s, r) in enumerate(zip(sides, ratios)):
+        mesh = grid_mesh_2d(int(s), int(s), jitter=jitter, seed=seed * 1000 + i)
+        inst = droplet_instance(mesh, radius=0.25 * s, rho_l=1.0, rho_v=1.0 / r, sigma=sigma, xi=xi,
+                                tau_l=tau, tau_v=tau, center=np.array([s / 2.0, s / 2.0]))
+        inst.meta.update(side=int(s), ratio=float(r))
+        insts.append(inst)
+    return Workload(f"ensemble2d_{count}", 9, insts, steps,
+                    "independent D2Q9 droplets of uneven size advanced together")
+
+
+WORKLOADS = {
+    "droplet2d": droplet2d,
+    "channel2d": channel2d,
+    "rt2d": rt2d,
+    "droplet3d": droplet3d,
+    "ensemble2d": ensemble2d,
+}
