@@ -1,0 +1,924 @@
+// Host side of the felbm C ABI: mesh validation and P1 assembly, device
+// layout, workspace sub-allocation, step scheduling (HIP graph replay) and
+// read-back.  See include/felbm.h for the contract of each entry point.
+#include "../../include/felbm.h"
+#include "felbm_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace fel;
+
+namespace {
+
+constexpr double CS2 = 1.0 / 3.0;
+
+struct LatticeInfo {
+    int Q, D, NB;
+    int e[19][3];
+    double w[19];
+};
+
+LatticeInfo make_lattice_info(int Q) {
+    LatticeInfo L{};
+    L.Q = Q;
+    if (Q == 9) {
+        const int E[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+                             {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+        L.D = 2;
+        L.NB = 5;
+        for (int a = 0; a < 9; a++) {
+            for (int r = 0; r < 3; r++) L.e[a][r] = E[a][r];
+            L.w[a] = a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        }
+    } else {
+        const int E[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                              {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                              {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                              {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+        L.D = 3;
+        L.NB = 9;
+        for (int a = 0; a < 19; a++) {
+            for (int r = 0; r < 3; r++) L.e[a][r] = E[a][r];
+            L.w[a] = a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+        }
+    }
+    return L;
+}
+
+// Assembled operators of one instance in local node numbering, row-major
+// ELL with the diagonal in slot 0.
+struct HostMesh {
+    bool present = false;
+    int dim = 0;
+    int64_t N = 0;
+    int W = 0;                    // max row length
+    std::vector<int32_t> col;     // [N][W] (-1 = empty slot)
+    std::vector<double> M;        // [N][W]
+    std::vector<double> basis;    // [NB][N][W]
+    std::vector<double> m;        // [N] lumped mass
+    std::vector<uint32_t> wmask;  // [N]
+};
+
+struct Instance {
+    HostMesh mesh;
+    bool have_phys = false;
+    fel_phys phys{};
+    InstParams P{};
+};
+
+struct ProfEvent {
+    int cls;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct fel_ctx {
+    fel_options opt{};
+    LatticeInfo lat{};
+    std::vector<Instance> inst;
+    int ninst = 0;
+    // layout
+    bool bound = false;
+    int W = 0, NB = 0, NP = 0;
+    int64_t R = 0;
+    int ntiles = 0;
+    size_t ws_bytes = 0;
+    int cg_iters = 0;
+    double cg_tol = 0.0;
+    DevLayout L{};
+    hipStream_t stream = nullptr;
+    char* dev = nullptr;
+    std::vector<int32_t> tile_inst;
+    // offsets in the workspace
+    struct Off {
+        size_t col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, rho, grad,
+            mu, S, u, p, partial, counter, rz, rz0, alpha, beta, sums, status, end;
+    } off{};
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool use_graph = true;
+    // profiling
+    bool profiling = false;
+    std::vector<ProfEvent> pending;
+    std::vector<hipEvent_t> event_pool;
+    int64_t prof_count[KC_COUNT] = {};
+    double prof_ms[KC_COUNT] = {};
+    std::string err;
+};
+
+namespace {
+
+fel_status fail(fel_ctx* c, fel_status s, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                    \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(ctx, FEL_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+int elem_size(int precision) { return precision == 0 ? 8 : 4; }
+
+// Element volume and shape-function gradients from the unwrapped vertices:
+// 2-D: grad N_1 = (y_2 - y_0, x_0 - x_2) / 2A, grad N_2 = (y_0 - y_1, x_1 - x_0) / 2A;
+// 3-D: grad N_1 = (x_2 - x_0) x (x_3 - x_0) / 6V and cyclic; grad N_0 = -sum.
+bool element_gradients(int dim, const double X[4][3], double* vol, double g[4][3]) {
+    if (dim == 2) {
+        const double ax = X[1][0] - X[0][0], ay = X[1][1] - X[0][1];
+        const double bx = X[2][0] - X[0][0], by = X[2][1] - X[0][1];
+        const double twoA = ax * by - ay * bx;
+        if (!(twoA > 0.0) || !std::isfinite(twoA)) return false;
+        *vol = 0.5 * twoA;
+        g[1][0] = by / twoA;
+        g[1][1] = -bx / twoA;
+        g[2][0] = -ay / twoA;
+        g[2][1] = ax / twoA;
+        g[0][0] = -(g[1][0] + g[2][0]);
+        g[0][1] = -(g[1][1] + g[2][1]);
+        return true;
+    }
+    double a[3], b[3], c[3];
+    for (int r = 0; r < 3; r++) {
+        a[r] = X[1][r] - X[0][r];
+        b[r] = X[2][r] - X[0][r];
+        c[r] = X[3][r] - X[0][r];
+    }
+    auto cross = [](const double* u, const double* v, double* o) {
+        o[0] = u[1] * v[2] - u[2] * v[1];
+        o[1] = u[2] * v[0] - u[0] * v[2];
+        o[2] = u[0] * v[1] - u[1] * v[0];
+    };
+    double bc[3], ca[3], ab[3];
+    cross(b, c, bc);
+    cross(c, a, ca);
+    cross(a, b, ab);
+    const double sixV = a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2];
+    if (!(sixV > 0.0) || !std::isfinite(sixV)) return false;
+    *vol = sixV / 6.0;
+    for (int r = 0; r < 3; r++) {
+        g[1][r] = bc[r] / sixV;
+        g[2][r] = ca[r] / sixV;
+        g[3][r] = ab[r] / sixV;
+        g[0][r] = -(g[1][r] + g[2][r] + g[3][r]);
+    }
+    return true;
+}
+
+int supported_width(int Q, int w) {
+    if (Q == 9) {
+        if (w <= 7) return 7;
+        if (w <= 12) return 12;
+    } else {
+        if (w <= 15) return 15;
+        if (w <= 24) return 24;
+    }
+    return -1;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* fel_version(void) { return "felbm 0.1 (gfx950)"; }
+
+const char* fel_last_error(const fel_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+fel_status fel_create(const fel_options* opt, fel_ctx** out) {
+    if (!opt || !out) return FEL_EINVAL;
+    *out = nullptr;
+    if (opt->lattice != 9 && opt->lattice != 19) return FEL_EINVAL;
+    if (opt->precision < 0 || opt->precision > 2) return FEL_EINVAL;
+    if (opt->mass_mode != 0 && opt->mass_mode != 1) return FEL_EINVAL;
+    if (opt->laplacian_mode != 0 && opt->laplacian_mode != 1) return FEL_EINVAL;
+    if (opt->max_instances < 1 || opt->max_instances > 65536) return FEL_EINVAL;
+    if (opt->cg_iters < 0 || opt->cg_iters > 1000 || opt->cg_tol < 0.0) return FEL_EINVAL;
+    fel_ctx* c = new (std::nothrow) fel_ctx();
+    if (!c) return FEL_ENOMEM;
+    c->opt = *opt;
+    c->lat = make_lattice_info(opt->lattice);
+    c->inst.resize(opt->max_instances);
+    const bool fp64 = opt->precision == 0;
+    const bool d2 = opt->lattice == 9;
+    c->cg_iters = opt->cg_iters ? opt->cg_iters : (d2 ? (fp64 ? 30 : 15) : (fp64 ? 34 : 17));
+    c->cg_tol = opt->cg_tol > 0.0 ? opt->cg_tol : (fp64 ? 1e-11 : 1e-5);
+    c->NP = 2 * (opt->lattice - 1);
+    c->NB = c->lat.NB;
+    *out = c;
+    return FEL_OK;
+}
+
+fel_status fel_upload_mesh(fel_ctx* c, int inst, int dim, int64_t n_nodes, const double* xyz, int64_t n_elems,
+                           const int32_t* conn, const int8_t* shift, const double* box, const uint8_t* wall,
+                           const double* wall_normal) {
+    if (!c) return FEL_EINVAL;
+    if (c->bound) return fail(c, FEL_EINVAL, "upload after bind");
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
+    if (dim != c->lat.D) return fail(c, FEL_EINVAL, "dim %d does not match lattice D%dQ%d", dim, c->lat.D, c->lat.Q);
+    if (n_nodes <= 0 || n_elems <= 0 || !xyz || !conn) return fail(c, FEL_EINVAL, "empty mesh");
+    if (n_nodes > (int64_t)1 << 30) return fail(c, FEL_EINVAL, "too many nodes");
+    if (shift && !box) return fail(c, FEL_EINVAL, "shift given without box");
+    const int nv = dim + 1;
+    const int NB = c->NB;
+    HostMesh hm;
+    hm.dim = dim;
+    hm.N = n_nodes;
+    // node -> elements
+    std::vector<int64_t> cnt(n_nodes + 1, 0);
+    for (int64_t e = 0; e < n_elems; e++)
+        for (int a = 0; a < nv; a++) {
+            const int32_t k = conn[e * nv + a];
+            if (k < 0 || k >= n_nodes) return fail(c, FEL_EINVAL, "element %lld vertex index %d out of range",
+                                                   (long long)e, k);
+            cnt[k + 1]++;
+        }
+    for (int64_t k = 0; k < n_nodes; k++) cnt[k + 1] += cnt[k];
+    std::vector<int64_t> n2e(cnt[n_nodes]);
+    {
+        std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+        for (int64_t e = 0; e < n_elems; e++)
+            for (int a = 0; a < nv; a++) n2e[pos[conn[e * nv + a]]++] = e;
+    }
+    // pattern: neighbours of each node (diagonal first, then ascending)
+    std::vector<std::vector<int32_t>> nbr(n_nodes);
+    int W = 0;
+    std::vector<int32_t> tmp;
+    for (int64_t k = 0; k < n_nodes; k++) {
+        tmp.clear();
+        for (int64_t i = cnt[k]; i < cnt[k + 1]; i++)
+            for (int a = 0; a < nv; a++) {
+                const int32_t v = conn[n2e[i] * nv + a];
+                if (v != k) tmp.push_back(v);
+            }
+        std::sort(tmp.begin(), tmp.end());
+        tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+        nbr[k].reserve(tmp.size() + 1);
+        nbr[k].push_back((int32_t)k);
+        nbr[k].insert(nbr[k].end(), tmp.begin(), tmp.end());
+        W = std::max<int>(W, (int)nbr[k].size());
+    }
+    hm.W = W;
+    hm.col.assign(n_nodes * W, -1);
+    for (int64_t k = 0; k < n_nodes; k++)
+        for (size_t s = 0; s < nbr[k].size(); s++) hm.col[k * W + s] = nbr[k][s];
+    nbr.clear();
+    nbr.shrink_to_fit();
+    hm.M.assign(n_nodes * W, 0.0);
+    hm.basis.assign((size_t)NB * n_nodes * W, 0.0);
+    hm.m.assign(n_nodes, 0.0);
+    const double mdiag = 2.0 / (nv * (nv + 1)), moff = 1.0 / (nv * (nv + 1));
+    for (int64_t e = 0; e < n_elems; e++) {
+        double X[4][3] = {{0}};
+        int32_t v[4];
+        for (int a = 0; a < nv; a++) {
+            v[a] = conn[e * nv + a];
+            for (int r = 0; r < dim; r++) {
+                const double s = shift ? (double)shift[(e * nv + a) * dim + r] * box[r] : 0.0;
+                X[a][r] = xyz[(int64_t)v[a] * dim + r] + s;
+            }
+        }
+        double vol, g[4][3] = {{0}};
+        if (!element_gradients(dim, X, &vol, g))
+            return fail(c, FEL_EINVAL, "element %lld has non-positive volume", (long long)e);
+        for (int a = 0; a < nv; a++) {
+            const int64_t rowk = v[a];
+            hm.m[rowk] += vol / nv;
+            for (int b = 0; b < nv; b++) {
+                int slot = -1;
+                for (int s = 0; s < W; s++)
+                    if (hm.col[rowk * W + s] == v[b]) {
+                        slot = s;
+                        break;
+                    }
+                const int64_t i = rowk * W + slot;
+                hm.M[i] += vol * (a == b ? mdiag : moff);
+                // G_r[a][b] = int N_a d_r N_b = V / (d+1) d_r N_b
+                for (int r = 0; r < dim; r++) hm.basis[((size_t)r * n_nodes) * W + i] += vol / nv * g[b][r];
+                // K_rr and symmetrised K_rs + K_sr
+                int n = dim;
+                for (int r = 0; r < dim; r++) hm.basis[((size_t)(n++) * n_nodes) * W + i] += vol * g[a][r] * g[b][r];
+                for (int r = 0; r < dim; r++)
+                    for (int s = r + 1; s < dim; s++)
+                        hm.basis[((size_t)(n++) * n_nodes) * W + i] +=
+                            vol * (g[a][r] * g[b][s] + g[a][s] * g[b][r]);
+            }
+        }
+    }
+    // bounce-back masks at wall nodes
+    hm.wmask.assign(n_nodes, 0u);
+    if (wall) {
+        if (!wall_normal) return fail(c, FEL_EINVAL, "wall flags given without normals");
+        for (int64_t k = 0; k < n_nodes; k++) {
+            if (!wall[k]) continue;
+            uint32_t mask = 0;
+            for (int a = 0; a < c->lat.Q; a++) {
+                double cn = 0.0;
+                for (int r = 0; r < dim; r++) cn += c->lat.e[a][r] * wall_normal[k * dim + r];
+                if (cn > 1e-12) mask |= 1u << a;
+            }
+            hm.wmask[k] = mask;
+        }
+    }
+    hm.present = true;
+    c->inst[inst].mesh = std::move(hm);
+    return FEL_OK;
+}
+
+static fel_status plan_layout(fel_ctx* c) {
+    int n = 0;
+    while (n < (int)c->inst.size() && c->inst[n].mesh.present) n++;
+    for (int i = n; i < (int)c->inst.size(); i++)
+        if (c->inst[i].mesh.present) return fail(c, FEL_EINVAL, "instances must be uploaded as 0..n-1");
+    if (n == 0) return fail(c, FEL_ESTATE, "no mesh uploaded");
+    c->ninst = n;
+    int wmax = 0;
+    for (int i = 0; i < n; i++) wmax = std::max(wmax, c->inst[i].mesh.W);
+    c->W = supported_width(c->opt.lattice, wmax);
+    if (c->W < 0) return fail(c, FEL_EINVAL, "mesh valence %d above the supported ELL width", wmax);
+    int64_t rows = 0;
+    c->tile_inst.clear();
+    for (int i = 0; i < n; i++) {
+        InstParams& P = c->inst[i].P;
+        const int64_t N = c->inst[i].mesh.N;
+        const int64_t tiles = (N + TILE - 1) / TILE;
+        P.row_begin = (int)rows;
+        P.row_end = (int)(rows + N);
+        P.tile_begin = (int)(rows / TILE);
+        P.tile_count = (int)tiles;
+        for (int64_t t = 0; t < tiles; t++) c->tile_inst.push_back(i);
+        rows += tiles * TILE;
+    }
+    if (rows >= ((int64_t)1 << 31)) return fail(c, FEL_EINVAL, "too many rows");
+    c->R = rows;
+    c->ntiles = (int)(rows / TILE);
+    const size_t R = (size_t)rows;
+    const int W = c->W, NB = c->NB, NP = c->NP, Q = c->opt.lattice, D = c->lat.D;
+    const size_t s = elem_size(c->opt.precision);
+    const size_t sp = c->opt.precision == 0 ? 8 : (c->opt.precision == 1 ? 4 : 2);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    auto& f = c->off;
+    f.col = take(4 * W * R);
+    f.Mval = take(s * W * R);
+    f.basis = take(s * NB * W * R);
+    f.minv = take(s * R);
+    f.mlump = take(8 * R);
+    f.wmask = take(4 * R);
+    f.tile_inst = take(4 * (size_t)c->ntiles);
+    f.params = take(sizeof(InstParams) * n);
+    f.psi = take(sp * 2 * Q * R);
+    f.ref = take(c->opt.precision == 0 ? 0 : 4 * 2 * R);
+    f.X = take(s * NP * R);
+    f.Rv = take(s * NP * R);
+    f.Pa = take(s * NP * R);
+    f.Pb = take(s * NP * R);
+    f.rho = take(s * R);
+    f.grad = take(s * D * R);
+    f.mu = take(s * R);
+    f.S = take(s * D * R);
+    f.u = take(s * D * R);
+    f.p = take(s * R);
+    f.partial = take(8 * (size_t)c->ntiles * std::max(NP, 8));
+    f.counter = take(4 * (size_t)n);
+    f.rz = take(8 * (size_t)n * NP);
+    f.rz0 = take(8 * (size_t)n * NP);
+    f.alpha = take(8 * (size_t)n * NP);
+    f.beta = take(8 * (size_t)n * NP);
+    f.sums = take(8 * 8 * (size_t)n);
+    f.status = take(4);
+    f.end = o;
+    c->ws_bytes = o;
+    return FEL_OK;
+}
+
+fel_status fel_workspace_size(fel_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return FEL_EINVAL;
+    if (!c->bound) {
+        fel_status st = plan_layout(c);
+        if (st != FEL_OK) return st;
+    }
+    *bytes = c->ws_bytes;
+    return FEL_OK;
+}
+
+static fel_status upload_operators(fel_ctx* c) {
+    const size_t R = c->R;
+    const int W = c->W, NB = c->NB;
+    const bool fp64 = c->opt.precision == 0;
+    const size_t s = elem_size(c->opt.precision);
+    std::vector<int32_t> col(W * R);
+    std::vector<double> Mv(W * R, 0.0), basis((size_t)NB * W * R, 0.0), minv(R, 1.0), mlump(R, 0.0);
+    std::vector<uint32_t> wmask(R, 0u);
+    for (size_t r = 0; r < R; r++)
+        for (int k = 0; k < W; k++) col[k * R + r] = (int32_t)r;
+    for (int i = 0; i < c->ninst; i++) {
+        const HostMesh& hm = c->inst[i].mesh;
+        const int64_t rb = c->inst[i].P.row_begin;
+        for (int64_t k = 0; k < hm.N; k++) {
+            const size_t row = rb + k;
+            for (int sl = 0; sl < hm.W; sl++) {
+                const int32_t cl = hm.col[k * hm.W + sl];
+                if (cl < 0) continue;
+                col[sl * R + row] = (int32_t)(rb + cl);
+                Mv[sl * R + row] = hm.M[k * hm.W + sl];
+                for (int n = 0; n < NB; n++)
+                    basis[((size_t)n * W + sl) * R + row] = hm.basis[((size_t)n * hm.N + k) * hm.W + sl];
+            }
+            minv[row] = 1.0 / hm.m[k];
+            mlump[row] = hm.m[k];
+            wmask[row] = hm.wmask[k];
+        }
+    }
+    auto put = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        return hipMemcpyAsync(c->dev + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+    };
+    auto put_t = [&](size_t off, const std::vector<double>& v) -> hipError_t {
+        if (fp64) return put(off, v.data(), v.size() * 8);
+        std::vector<float> t(v.size());
+        for (size_t i = 0; i < v.size(); i++) t[i] = (float)v[i];
+        hipError_t e = put(off, t.data(), t.size() * 4);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        return e;
+    };
+    (void)s;
+    HIP_TRY(c, put(c->off.col, col.data(), col.size() * 4));
+    HIP_TRY(c, put_t(c->off.Mval, Mv));
+    HIP_TRY(c, put_t(c->off.basis, basis));
+    HIP_TRY(c, put_t(c->off.minv, minv));
+    HIP_TRY(c, put(c->off.mlump, mlump.data(), R * 8));
+    HIP_TRY(c, put(c->off.wmask, wmask.data(), R * 4));
+    HIP_TRY(c, put(c->off.tile_inst, c->tile_inst.data(), c->tile_inst.size() * 4));
+    HIP_TRY(c, hipMemsetAsync(c->dev + c->off.counter, 0, 4 * c->ninst, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->dev + c->off.status, 0, 4, c->stream));
+    // padding rows of every vector start at zero
+    HIP_TRY(c, hipMemsetAsync(c->dev + c->off.psi, 0, c->off.X - c->off.psi, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->dev + c->off.X, 0, c->off.partial - c->off.X, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FEL_OK;
+}
+
+static void set_pointers(fel_ctx* c) {
+    DevLayout& L = c->L;
+    char* d = c->dev;
+    const auto& f = c->off;
+    L.R = c->R;
+    L.W = c->W;
+    L.NB = c->NB;
+    L.Q = c->opt.lattice;
+    L.dim = c->lat.D;
+    L.ninst = c->ninst;
+    L.ntiles = c->ntiles;
+    L.precision = c->opt.precision;
+    L.col = reinterpret_cast<const int32_t*>(d + f.col);
+    L.Mval = d + f.Mval;
+    L.basis = d + f.basis;
+    L.minv = d + f.minv;
+    L.mlump = reinterpret_cast<const double*>(d + f.mlump);
+    L.wmask = reinterpret_cast<const uint32_t*>(d + f.wmask);
+    L.tile_inst = reinterpret_cast<const int32_t*>(d + f.tile_inst);
+    L.params = reinterpret_cast<const InstParams*>(d + f.params);
+    L.psi = d + f.psi;
+    L.ref = c->opt.precision == 0 ? nullptr : reinterpret_cast<float*>(d + f.ref);
+    L.X = d + f.X;
+    L.Rv = d + f.Rv;
+    L.Pa = d + f.Pa;
+    L.Pb = d + f.Pb;
+    L.rho = d + f.rho;
+    L.grad = d + f.grad;
+    L.mu = d + f.mu;
+    L.S = d + f.S;
+    L.u = d + f.u;
+    L.p = d + f.p;
+    L.partial = reinterpret_cast<double*>(d + f.partial);
+    L.counter = reinterpret_cast<int32_t*>(d + f.counter);
+    L.rz = reinterpret_cast<double*>(d + f.rz);
+    L.rz0 = reinterpret_cast<double*>(d + f.rz0);
+    L.alpha = reinterpret_cast<double*>(d + f.alpha);
+    L.beta = reinterpret_cast<double*>(d + f.beta);
+    L.sums = reinterpret_cast<double*>(d + f.sums);
+    L.status = reinterpret_cast<uint32_t*>(d + f.status);
+    L.cg_tol2 = c->cg_tol * c->cg_tol;
+    L.lap_mode = c->opt.laplacian_mode;
+}
+
+fel_status fel_bind(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
+    if (!c || !dev_ptr) return FEL_EINVAL;
+    if (c->bound) return fail(c, FEL_ESTATE, "already bound");
+    if (((uintptr_t)dev_ptr) & 255) return fail(c, FEL_EINVAL, "workspace must be 256-byte aligned");
+    fel_status st = plan_layout(c);
+    if (st != FEL_OK) return st;
+    if (bytes < c->ws_bytes)
+        return fail(c, FEL_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, c->ws_bytes);
+    c->dev = static_cast<char*>(dev_ptr);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    set_pointers(c);
+    st = upload_operators(c);
+    if (st != FEL_OK) return st;
+    // host copies of the assembled operators are no longer needed
+    for (int i = 0; i < c->ninst; i++) {
+        HostMesh& hm = c->inst[i].mesh;
+        std::vector<int32_t>().swap(hm.col);
+        std::vector<double>().swap(hm.M);
+        std::vector<double>().swap(hm.basis);
+        std::vector<uint32_t>().swap(hm.wmask);
+    }
+    c->bound = true;
+    // graphs cannot be captured on the legacy default stream
+    c->use_graph = c->stream != nullptr;
+    return FEL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// launches
+
+namespace {
+
+hipEvent_t get_event(fel_ctx* c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <typename F>
+hipError_t timed(fel_ctx* c, int cls, F&& launch) {
+    if (!c->profiling) return launch();
+    ProfEvent pe{cls, get_event(c), get_event(c)};
+    if (pe.a) (void)hipEventRecord(pe.a, c->stream);
+    hipError_t e = launch();
+    if (pe.b) (void)hipEventRecord(pe.b, c->stream);
+    c->pending.push_back(pe);
+    return e;
+}
+
+hipError_t enqueue_solve(fel_ctx* c, int tb, int nt) {
+    const DevLayout& L = c->L;
+    hipStream_t s = c->stream;
+    hipError_t e;
+    if (c->opt.mass_mode == FEL_MASS_LUMPED) {
+        return timed(c, KC_LUMPED, [&] { return launch_lumped(L, tb, nt, s); });
+    }
+    if ((e = timed(c, KC_CG_INIT, [&] { return launch_cg_init(L, tb, nt, s); })) != hipSuccess) return e;
+    for (int it = 0; it < c->cg_iters; it++) {
+        const bool flip = (it & 1) != 0;
+        if ((e = timed(c, KC_CG_A, [&] { return launch_cg_a(L, tb, nt, it == 0, flip, s); })) != hipSuccess)
+            return e;
+        if ((e = timed(c, KC_CG_B, [&] { return launch_cg_b(L, tb, nt, it == c->cg_iters - 1, flip, s); })) !=
+            hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t enqueue_step(fel_ctx* c) {
+    const DevLayout& L = c->L;
+    hipStream_t s = c->stream;
+    const int nt = c->ntiles;
+    hipError_t e;
+    if ((e = timed(c, KC_STREAM, [&] { return launch_stream(L, 0, nt, s); })) != hipSuccess) return e;
+    if ((e = enqueue_solve(c, 0, nt)) != hipSuccess) return e;
+    if ((e = timed(c, KC_MOMENTS, [&] { return launch_moments(L, 0, nt, s); })) != hipSuccess) return e;
+    if ((e = timed(c, KC_GRAD, [&] { return launch_grad(L, 0, nt, s); })) != hipSuccess) return e;
+    if ((e = timed(c, KC_DIV, [&] { return launch_div(L, 0, nt, s); })) != hipSuccess) return e;
+    if ((e = timed(c, KC_COLLIDE, [&] { return launch_collide(L, 0, nt, s); })) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+fel_status drain_profile(fel_ctx* c) {
+    if (c->pending.empty()) return FEL_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& pe : c->pending) {
+        float ms = 0.0f;
+        if (pe.a && pe.b && hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+            c->prof_ms[pe.cls] += ms;
+            c->prof_count[pe.cls]++;
+        }
+        if (pe.a) c->event_pool.push_back(pe.a);
+        if (pe.b) c->event_pool.push_back(pe.b);
+    }
+    c->pending.clear();
+    return FEL_OK;
+}
+
+bool all_initialised(const fel_ctx* c) {
+    for (int i = 0; i < c->ninst; i++)
+        if (!c->inst[i].have_phys) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+fel_status fel_init_fields(fel_ctx* c, int inst, const fel_phys* ph, const double* rho, const double* u,
+                           const double* p) {
+    if (!c || !ph || !rho) return FEL_EINVAL;
+    if (!c->bound) return fail(c, FEL_ESTATE, "init_fields before bind");
+    if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
+    const double drho = ph->rho_l - ph->rho_v;
+    if (!(drho > 0.0) || !(ph->rho_v > 0.0) || !(ph->tau_l > 0.0) || !(ph->tau_v > 0.0) || !(ph->dt > 0.0) ||
+        !(ph->xi > 0.0) || !(ph->sigma >= 0.0))
+        return fail(c, FEL_EINVAL, "invalid physical parameters");
+    Instance& I = c->inst[inst];
+    const int64_t N = I.mesh.N;
+    const int D = c->lat.D;
+    for (int64_t k = 0; k < N; k++)
+        if (!std::isfinite(rho[k]) || !(rho[k] > 0.0)) return fail(c, FEL_EINVAL, "rho must be finite and positive");
+    I.phys = *ph;
+    InstParams& P = I.P;
+    P.rho_l = ph->rho_l;
+    P.rho_v = ph->rho_v;
+    P.tau_l = ph->tau_l;
+    P.tau_v = ph->tau_v;
+    P.dt = ph->dt;
+    for (int r = 0; r < 3; r++) P.grav[r] = r < D ? ph->grav[r] : 0.0;
+    P.beta = 12.0 * ph->sigma / (ph->xi * drho * drho * drho * drho);
+    P.kappa = 1.5 * ph->xi * ph->sigma / (drho * drho);
+    P.scale = 1.0;
+    HIP_TRY(c, hipMemcpyAsync(c->dev + c->off.params + sizeof(InstParams) * inst, &P, sizeof(InstParams),
+                              hipMemcpyHostToDevice, c->stream));
+    const bool fp64 = c->opt.precision == 0;
+    const size_t R = c->R;
+    // upload rho, u, p into the field arrays at the instance rows
+    auto put_field = [&](size_t off, int comp, const double* src, int stride) -> hipError_t {
+        std::vector<double> v(N);
+        for (int64_t k = 0; k < N; k++) v[k] = src ? src[k * stride + comp] : 0.0;
+        const size_t at = off + ((size_t)comp * R + P.row_begin) * (fp64 ? 8 : 4);
+        if (fp64) {
+            hipError_t e = hipMemcpyAsync(c->dev + at, v.data(), N * 8, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            return e;
+        }
+        std::vector<float> t(N);
+        for (int64_t k = 0; k < N; k++) t[k] = (float)v[k];
+        hipError_t e = hipMemcpyAsync(c->dev + at, t.data(), N * 4, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        return e;
+    };
+    HIP_TRY(c, put_field(c->off.rho, 0, rho, 1));
+    for (int r = 0; r < D; r++) HIP_TRY(c, put_field(c->off.u, r, u, D));
+    HIP_TRY(c, put_field(c->off.p, 0, p, 1));
+    const int tb = P.tile_begin, nt = P.tile_count;
+    HIP_TRY(c, launch_grad(c->L, tb, nt, c->stream));
+    HIP_TRY(c, launch_div(c->L, tb, nt, c->stream));
+    HIP_TRY(c, launch_init(c->L, tb, nt, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    I.have_phys = true;
+    return FEL_OK;
+}
+
+fel_status fel_step(fel_ctx* c, int n_steps) {
+    if (!c || n_steps < 0) return FEL_EINVAL;
+    if (!c->bound || !all_initialised(c)) return fail(c, FEL_ESTATE, "step before bind/init_fields");
+    if (n_steps == 0) return FEL_OK;
+    if (c->profiling || !c->use_graph) {
+        for (int i = 0; i < n_steps; i++) {
+            hipError_t e = enqueue_step(c);
+            if (e != hipSuccess) return fail(c, FEL_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+            if (c->profiling && c->pending.size() > 4096) {
+                fel_status st = drain_profile(c);
+                if (st != FEL_OK) return st;
+            }
+        }
+        return c->profiling ? drain_profile(c) : FEL_OK;
+    }
+    if (!c->graph_exec) {
+        HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_step(c);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(c, FEL_EDEVICE, "graph capture failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        c->graph = g;
+        HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    }
+    for (int i = 0; i < n_steps; i++) HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+    return FEL_OK;
+}
+
+fel_status fel_sync(fel_ctx* c) {
+    if (!c) return FEL_EINVAL;
+    if (!c->bound) return fail(c, FEL_ESTATE, "sync before bind");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    uint32_t st = 0;
+    HIP_TRY(c, hipMemcpy(&st, c->dev + c->off.status, 4, hipMemcpyDeviceToHost));
+    if (st) {
+        const uint32_t zero = 0;
+        HIP_TRY(c, hipMemcpy(c->dev + c->off.status, &zero, 4, hipMemcpyHostToDevice));
+    }
+    if (st & 1u) return fail(c, FEL_ENONFINITE, "non-finite population or field");
+    if (st & 2u) return fail(c, FEL_ENOTCONV, "CG residual above tolerance after %d iterations", c->cg_iters);
+    return FEL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// copy `count` rows of a device array of element size s (8 or 4) into doubles
+fel_status read_rows(fel_ctx* c, size_t off, int64_t first, int64_t count, double* out, int stride, int comp) {
+    const bool fp64 = c->opt.precision == 0;
+    const size_t es = fp64 ? 8 : 4;
+    if (fp64) {
+        std::vector<double> v(count);
+        HIP_TRY(c, hipMemcpy(v.data(), c->dev + off + first * es, count * es, hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < count; k++) out[k * stride + comp] = v[k];
+    } else {
+        std::vector<float> v(count);
+        HIP_TRY(c, hipMemcpy(v.data(), c->dev + off + first * es, count * es, hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < count; k++) out[k * stride + comp] = v[k];
+    }
+    return FEL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fel_status fel_read_fields(fel_ctx* c, int inst, double* rho, double* u, double* p, double* C) {
+    if (!c) return FEL_EINVAL;
+    if (!c->bound) return fail(c, FEL_ESTATE, "read before bind");
+    if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
+    const Instance& I = c->inst[inst];
+    if (!I.have_phys) return fail(c, FEL_ESTATE, "instance %d not initialised", inst);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int64_t N = I.mesh.N, rb = I.P.row_begin;
+    const int D = c->lat.D;
+    const size_t R = c->R;
+    fel_status st;
+    std::vector<double> r(N);
+    if ((st = read_rows(c, c->off.rho, rb, N, r.data(), 1, 0)) != FEL_OK) return st;
+    if (rho) std::copy(r.begin(), r.end(), rho);
+    if (C)
+        for (int64_t k = 0; k < N; k++) C[k] = (r[k] - I.phys.rho_v) / (I.phys.rho_l - I.phys.rho_v);
+    if (u)
+        for (int d = 0; d < D; d++)
+            if ((st = read_rows(c, c->off.u, (int64_t)d * R + rb, N, u, D, d)) != FEL_OK) return st;
+    if (p && (st = read_rows(c, c->off.p, rb, N, p, 1, 0)) != FEL_OK) return st;
+    return FEL_OK;
+}
+
+fel_status fel_conserved_sums(fel_ctx* c, int inst, double out[6]) {
+    if (!c || !out) return FEL_EINVAL;
+    if (!c->bound) return fail(c, FEL_ESTATE, "sums before bind");
+    if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
+    const InstParams& P = c->inst[inst].P;
+    if (!c->inst[inst].have_phys) return fail(c, FEL_ESTATE, "instance %d not initialised", inst);
+    HIP_TRY(c, launch_sums(c->L, P.tile_begin, P.tile_count, c->stream));
+    double v[8];
+    HIP_TRY(c, hipMemcpyAsync(v, c->dev + c->off.sums + 64 * inst, 64, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 6; i++) out[i] = v[i];
+    return FEL_OK;
+}
+
+fel_status fel_get_state(fel_ctx* c, int inst, double* psibar) {
+    if (!c || !psibar) return FEL_EINVAL;
+    if (!c->bound) return fail(c, FEL_ESTATE, "get_state before bind");
+    if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
+    if (c->opt.precision != 0) return fail(c, FEL_EINVAL, "state read-back for this precision not built yet");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const Instance& I = c->inst[inst];
+    const int64_t N = I.mesh.N;
+    for (int a = 0; a < 2 * c->opt.lattice; a++)
+        HIP_TRY(c, hipMemcpy(psibar + a * N, c->dev + c->off.psi + ((size_t)a * c->R + I.P.row_begin) * 8, N * 8,
+                             hipMemcpyDeviceToHost));
+    return FEL_OK;
+}
+
+fel_status fel_set_state(fel_ctx* c, int inst, const double* psibar) {
+    if (!c || !psibar) return FEL_EINVAL;
+    if (!c->bound) return fail(c, FEL_ESTATE, "set_state before bind");
+    if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
+    if (!c->inst[inst].have_phys) return fail(c, FEL_ESTATE, "set_state needs init_fields first");
+    if (c->opt.precision != 0) return fail(c, FEL_EINVAL, "state upload for this precision not built yet");
+    const Instance& I = c->inst[inst];
+    const int64_t N = I.mesh.N;
+    for (int a = 0; a < 2 * c->opt.lattice; a++)
+        HIP_TRY(c, hipMemcpy(c->dev + c->off.psi + ((size_t)a * c->R + I.P.row_begin) * 8, psibar + a * N, N * 8,
+                             hipMemcpyHostToDevice));
+    return FEL_OK;
+}
+
+fel_status fel_read_aux(fel_ctx* c, int inst, int which, double* out) {
+    if (!c || !out) return FEL_EINVAL;
+    if (!c->bound) return fail(c, FEL_ESTATE, "read_aux before bind");
+    if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const Instance& I = c->inst[inst];
+    const int64_t N = I.mesh.N, rb = I.P.row_begin;
+    const int D = c->lat.D, Q = c->opt.lattice;
+    const size_t R = c->R;
+    fel_status st = FEL_OK;
+    switch (which) {
+    case FEL_AUX_GRADRHO:
+        for (int d = 0; d < D && st == FEL_OK; d++) st = read_rows(c, c->off.grad, (int64_t)d * R + rb, N, out, D, d);
+        return st;
+    case FEL_AUX_MU:
+        return read_rows(c, c->off.mu, rb, N, out, 1, 0);
+    case FEL_AUX_S:
+        for (int d = 0; d < D && st == FEL_OK; d++) st = read_rows(c, c->off.S, (int64_t)d * R + rb, N, out, D, d);
+        return st;
+    case FEL_AUX_DELTA:
+        for (int64_t k = 0; k < N; k++) {
+            out[k] = 0.0;
+            out[Q * N + k] = 0.0;
+        }
+        for (int j = 0; j < c->NP && st == FEL_OK; j++) {
+            const int pop = j < Q - 1 ? j + 1 : Q + (j - (Q - 1)) + 1;
+            st = read_rows(c, c->off.X, (int64_t)j * R + rb, N, out + pop * N, 1, 0);
+        }
+        return st;
+    default:
+        return fail(c, FEL_EINVAL, "unknown aux field %d", which);
+    }
+}
+
+fel_status fel_profile(fel_ctx* c, int enable) {
+    if (!c) return FEL_EINVAL;
+    if (!enable) {
+        drain_profile(c);
+        for (int k = 0; k < KC_COUNT; k++) {
+            c->prof_count[k] = 0;
+            c->prof_ms[k] = 0.0;
+        }
+    }
+    c->profiling = enable != 0;
+    return FEL_OK;
+}
+
+fel_status fel_profile_read(fel_ctx* c, int max_classes, int* n_classes, int64_t* counts, double* total_ms,
+                            const char** names) {
+    if (!c || !n_classes) return FEL_EINVAL;
+    fel_status st = drain_profile(c);
+    if (st != FEL_OK) return st;
+    *n_classes = KC_COUNT;
+    for (int k = 0; k < KC_COUNT && k < max_classes; k++) {
+        if (counts) counts[k] = c->prof_count[k];
+        if (total_ms) total_ms[k] = c->prof_ms[k];
+        if (names) names[k] = kernel_class_name(k);
+    }
+    return FEL_OK;
+}
+
+fel_status fel_layout_info(fel_ctx* c, int64_t* rows, int* ell_width, int* pops, int* cg_iters) {
+    if (!c) return FEL_EINVAL;
+    if (!c->bound) {
+        fel_status st = plan_layout(c);
+        if (st != FEL_OK) return st;
+    }
+    if (rows) *rows = c->R;
+    if (ell_width) *ell_width = c->W;
+    if (pops) *pops = 2 * c->opt.lattice;
+    if (cg_iters) *cg_iters = c->opt.mass_mode == FEL_MASS_LUMPED ? 0 : c->cg_iters;
+    return FEL_OK;
+}
+
+fel_status fel_destroy(fel_ctx* c) {
+    if (!c) return FEL_OK;
+    if (c->bound && c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto& pe : c->pending) {
+        if (pe.a) (void)hipEventDestroy(pe.a);
+        if (pe.b) (void)hipEventDestroy(pe.b);
+    }
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    delete c;
+    return FEL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Private layout shared by the host side (felbm_host.cpp) and the kernels
+// (felbm_kernels.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace fel {
+
+// Rows are processed in tiles of TILE rows (one block per tile); every
+// instance starts on a tile boundary so a tile never mixes instances and a
+// block's reduction partials belong to one instance.
+constexpr int TILE = 256;
+
+// Per-instance physics and layout, resident on the device.
+struct InstParams {
+    double rho_l, rho_v, tau_l, tau_v, dt;
+    double grav[3];
+    double beta, kappa;
+    double scale;          // deviation scale s (FP32 modes): psi_a = w_a (ref + s d_a)
+    int row_begin, row_end;  // valid rows of the instance [row_begin, row_end)
+    int tile_begin, tile_count;
+};
+
+// Device pointers of one context (all sub-allocated in the bound workspace).
+// R = total padded rows, W = ELL width, NB = stream basis matrices
+// (2-D: Gx Gy Kxx Kyy Kxy; 3-D: Gx Gy Gz Kxx Kyy Kzz Kxy Kxz Kyz, where
+// K_rs here is K_rs + K_sr for r != s).
+struct DevLayout {
+    int64_t R;
+    int W, NB, Q, dim, ninst, ntiles;
+    int precision;         // 0 fp64, 1 fp32, 2 fp32 with fp16 deviations
+    // pattern and operators, ELL slot-major: value[k * R + row]
+    const int32_t* col;
+    const void* Mval;      // T [W][R]
+    const void* basis;     // T [NB][W][R]
+    const void* minv;      // T [R]   1/m (1 on padding rows)
+    const double* mlump;   // double [R] lumped mass (0 on padding rows)
+    const uint32_t* wmask; // [R] bit a set: population a takes its opposite after streaming
+    const int32_t* tile_inst;   // [ntiles]
+    const InstParams* params;   // [ninst]
+    // populations
+    void* psi;             // FP64: double [2Q][R];  FP32 modes: deviations float/half [2Q][R]
+    float* ref;            // FP32 modes: [2][R] reference of f (rho) and g (p / cs^2)
+    // CG work vectors over the 2(Q-1) moving populations, T [2(Q-1)][R]
+    void* X;
+    void* Rv;
+    void* Pa;
+    void* Pb;
+    // nodal fields, T
+    void* rho;             // [R]
+    void* grad;            // [dim][R]
+    void* mu;              // [R]
+    void* S;               // [dim][R]
+    void* u;               // [dim][R]
+    void* p;               // [R]
+    // reductions
+    double* partial;       // [ntiles][2(Q-1)] (also reused for the conserved sums)
+    int32_t* counter;      // [ninst]
+    double* rz;            // [ninst][2(Q-1)]
+    double* rz0;           // [ninst][2(Q-1)]
+    double* alpha;         // [ninst][2(Q-1)]
+    double* beta;          // [ninst][2(Q-1)]
+    double* sums;          // [ninst][8]
+    uint32_t* status;      // [1] bit 0 non-finite, bit 1 CG residual above tolerance
+    double cg_tol2;        // squared relative residual tolerance of the CG check
+    int lap_mode;          // 0 nested recovery, 1 weak form
+};
+
+enum KernelClass {
+    KC_STREAM = 0,
+    KC_CG_INIT,
+    KC_CG_A,
+    KC_CG_B,
+    KC_LUMPED,
+    KC_MOMENTS,
+    KC_GRAD,
+    KC_DIV,
+    KC_COLLIDE,
+    KC_INIT,
+    KC_SUMS,
+    KC_COUNT
+};
+
+const char* kernel_class_name(int k);
+
+// Launchers (felbm_kernels.hip).  tile_begin/ntiles select the tile range;
+// every launcher returns the hipError_t of the launch.
+hipError_t launch_stream(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, bool flip, hipStream_t s);
+hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool last, bool flip, hipStream_t s);
+hipError_t launch_lumped(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+hipError_t launch_moments(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+hipError_t launch_grad(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+hipError_t launch_div(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+hipError_t launch_collide(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+hipError_t launch_init(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+hipError_t launch_sums(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+
+}  // namespace fel

@@ -152,7 +152,7 @@ def channel_profile(y, *, half_width, core, rho_heavy, rho_light, tau_heavy, tau
 
 
 def channel2d(nx=1024, ny=256, *, jitter=0.2, seed=1609, rho_heavy=1.0, rho_light=1e-3,
-              tau_heavy=0.05, tau_light=1.0, sigma=0.01, xi=4.0, g=1e-7, steps=5000) -> Workload:
+              tau_heavy=0.05, tau_light=1.0, sigma=0.01, xi=12.0, g=1e-7, steps=5000) -> Workload:
     """Layered Poiseuille flow: heavy fluid along both walls, light core.
 
     Walls are the node rows y = 0 and y = ny-1; flow along periodic x.

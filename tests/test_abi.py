@@ -1,0 +1,85 @@
+"""C ABI of libfelbm.so without a GPU: every declared symbol is exported,
+and the host-side validation (options, mesh checks, layout sizing) returns
+the documented status codes.  No device call is made here."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1608_01906_amd import felbm
+from paper_1608_01906_amd.inputs import grid_mesh_2d, grid_mesh_3d
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "felbm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"FEL_API[^;]*?\b(fel_[a-z_]+)\s*\(", text, re.S)))
+
+
+def test_all_declared_symbols_exported():
+    declared = _declared()
+    assert len(declared) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", felbm.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (fel_[a-z_]+)", out))
+    assert set(declared) <= exported, set(declared) - exported
+    assert sorted(felbm.ABI_SYMBOLS) == declared
+    assert felbm.load_library().fel_version().startswith(b"felbm")
+
+
+def test_bad_options_rejected():
+    for kw in [dict(precision="fp64", max_instances=0)]:
+        with pytest.raises(felbm.FelError):
+            felbm.Context(9, **kw)
+    with pytest.raises(felbm.FelError):
+        felbm.Context(7)
+
+
+def test_inverted_element_rejected():
+    m = grid_mesh_2d(4, 4)
+    m["conn"] = m["conn"][:, [0, 2, 1]].copy()
+    m["shift"] = m["shift"][:, [0, 2, 1]].copy()
+    ctx = felbm.Context(9)
+    with pytest.raises(felbm.FelError) as ei:
+        ctx.upload_mesh(0, m)
+    assert ei.value.status == felbm.FEL_EINVAL
+
+
+def test_index_out_of_range_rejected():
+    m = grid_mesh_2d(4, 4)
+    m["conn"] = m["conn"].copy()
+    m["conn"][3, 1] = 16
+    ctx = felbm.Context(9)
+    with pytest.raises(felbm.FelError) as ei:
+        ctx.upload_mesh(0, m)
+    assert ei.value.status == felbm.FEL_EINVAL
+
+
+def test_dimension_mismatch_and_order():
+    ctx = felbm.Context(9, max_instances=2)
+    with pytest.raises(felbm.FelError):
+        ctx.upload_mesh(0, grid_mesh_3d(3, 3, 3))
+    with pytest.raises(felbm.FelError):
+        ctx.upload_mesh(2, grid_mesh_2d(4, 4))
+    # step before bind
+    ctx.upload_mesh(0, grid_mesh_2d(4, 4))
+    with pytest.raises(felbm.FelError) as ei:
+        ctx.step(1)
+    assert ei.value.status == felbm.FEL_ESTATE
+
+
+def test_layout_padding_and_workspace():
+    ctx = felbm.Context(9, max_instances=3)
+    sizes = [(5, 5), (20, 13), (16, 16)]
+    for i, (a, b) in enumerate(sizes):
+        ctx.upload_mesh(i, grid_mesh_2d(a, b, seed=i))
+    info = ctx.layout_info()
+    assert info["rows"] == 256 * (1 + 2 + 1)   # every instance starts on a 256-row tile
+    assert info["ell_width"] == 7 and info["pops"] == 18 and info["cg_iters"] == 30
+    assert ctx.workspace_size() > 0
+    c3 = felbm.Context(19, precision="fp32")
+    c3.upload_mesh(0, grid_mesh_3d(4, 4, 4))
+    info = c3.layout_info()
+    assert info["ell_width"] == 15 and info["cg_iters"] == 17
