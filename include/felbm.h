@@ -73,6 +73,9 @@ typedef enum {
 #define FEL_MASS_CONSISTENT 0  /* solve with the consistent mass matrix (conjugate gradients) */
 #define FEL_MASS_LUMPED 1      /* lumped-mass approximation (end of Section 2.2.1) */
 
+#define FEL_ORDER_CALLER 0     /* device rows follow the caller's node order */
+#define FEL_ORDER_ZCURVE 1     /* device rows follow a Z-order (Morton) curve of the node positions */
+
 #define FEL_LAP_NESTED 0       /* Laplacian = recovered divergence of the recovered gradient */
 #define FEL_LAP_WEAK 1         /* Laplacian = -m^-1 (sum_r K_rr) rho (Galerkin, lumped mass) */
 
@@ -85,6 +88,10 @@ typedef struct {
                              0 = default (1e-11 FP64, 1e-5 FP32) */
     int laplacian_mode;   /* FEL_LAP_* */
     int max_instances;    /* number of independent meshes this context may hold (>= 1) */
+    int node_order;       /* FEL_ORDER_*: the row order of the device layout.  Row-major grids are
+                             already coalesced (each neighbour slot of 64 consecutive rows is one
+                             contiguous run); unstructured meshes in arbitrary order need the curve.
+                             Fields always cross the ABI in the caller's order. */
 } fel_options;
 
 /* Physical parameters of one instance (Section 2.1).  rho_l is the heavy

@@ -63,6 +63,7 @@ struct HostMesh {
     std::vector<double> basis;    // [NB][N][W]
     std::vector<double> m;        // [N] lumped mass
     std::vector<uint32_t> wmask;  // [N]
+    std::vector<int64_t> perm;    // [N] device order -> caller node index
 };
 
 struct Instance {
@@ -194,6 +195,43 @@ int supported_width(int Q, int w) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+uint64_t spread_bits(uint64_t v, int dim) {
+    uint64_t r = 0;
+    const int nbits = dim == 2 ? 31 : 21;
+    for (int b = 0; b < nbits; b++) r |= ((v >> b) & 1ull) << (b * dim);
+    return r;
+}
+
+// Device node order: Z-order (Morton) of the nodes quantised to the mean
+// spacing, so that a wavefront's 64 consecutive rows are a compact patch and
+// the neighbour gathers of a tile stay within a small halo.
+std::vector<int64_t> locality_order(int dim, int64_t n, const double* xyz) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t k = 0; k < n; k++)
+        for (int r = 0; r < dim; r++) {
+            lo[r] = std::min(lo[r], xyz[k * dim + r]);
+            hi[r] = std::max(hi[r], xyz[k * dim + r]);
+        }
+    double vol = 1.0;
+    for (int r = 0; r < dim; r++) vol *= std::max(hi[r] - lo[r], 1e-300);
+    const double h = std::pow(vol / (double)n, 1.0 / dim);
+    const double cap = dim == 2 ? 2147483647.0 : 2097151.0;
+    std::vector<uint64_t> key(n);
+    for (int64_t k = 0; k < n; k++) {
+        uint64_t code = 0;
+        for (int r = 0; r < dim; r++) {
+            double q = std::floor((xyz[k * dim + r] - lo[r]) / h + 0.5);
+            q = std::min(std::max(q, 0.0), cap);
+            code |= spread_bits((uint64_t)q, dim) << r;
+        }
+        key[k] = code;
+    }
+    std::vector<int64_t> perm(n);
+    for (int64_t k = 0; k < n; k++) perm[k] = k;
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+    return perm;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -213,6 +251,7 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
     if (opt->laplacian_mode != 0 && opt->laplacian_mode != 1) return FEL_EINVAL;
     if (opt->max_instances < 1 || opt->max_instances > 65536) return FEL_EINVAL;
     if (opt->cg_iters < 0 || opt->cg_iters > 1000 || opt->cg_tol < 0.0) return FEL_EINVAL;
+    if (opt->node_order != FEL_ORDER_CALLER && opt->node_order != FEL_ORDER_ZCURVE) return FEL_EINVAL;
     fel_ctx* c = new (std::nothrow) fel_ctx();
     if (!c) return FEL_ENOMEM;
     c->opt = *opt;
@@ -228,16 +267,11 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
     return FEL_OK;
 }
 
-fel_status fel_upload_mesh(fel_ctx* c, int inst, int dim, int64_t n_nodes, const double* xyz, int64_t n_elems,
+}  // extern "C"
+
+static fel_status assemble(fel_ctx* c, int inst, int dim, int64_t n_nodes, const double* xyz, int64_t n_elems,
                            const int32_t* conn, const int8_t* shift, const double* box, const uint8_t* wall,
-                           const double* wall_normal) {
-    if (!c) return FEL_EINVAL;
-    if (c->bound) return fail(c, FEL_EINVAL, "upload after bind");
-    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
-    if (dim != c->lat.D) return fail(c, FEL_EINVAL, "dim %d does not match lattice D%dQ%d", dim, c->lat.D, c->lat.Q);
-    if (n_nodes <= 0 || n_elems <= 0 || !xyz || !conn) return fail(c, FEL_EINVAL, "empty mesh");
-    if (n_nodes > (int64_t)1 << 30) return fail(c, FEL_EINVAL, "too many nodes");
-    if (shift && !box) return fail(c, FEL_EINVAL, "shift given without box");
+                           const double* wall_normal, std::vector<int64_t>&& perm) {
     const int nv = dim + 1;
     const int NB = c->NB;
     HostMesh hm;
@@ -327,7 +361,6 @@ fel_status fel_upload_mesh(fel_ctx* c, int inst, int dim, int64_t n_nodes, const
     // bounce-back masks at wall nodes
     hm.wmask.assign(n_nodes, 0u);
     if (wall) {
-        if (!wall_normal) return fail(c, FEL_EINVAL, "wall flags given without normals");
         for (int64_t k = 0; k < n_nodes; k++) {
             if (!wall[k]) continue;
             uint32_t mask = 0;
@@ -340,8 +373,52 @@ fel_status fel_upload_mesh(fel_ctx* c, int inst, int dim, int64_t n_nodes, const
         }
     }
     hm.present = true;
+    hm.perm = std::move(perm);
     c->inst[inst].mesh = std::move(hm);
     return FEL_OK;
+}
+
+extern "C" {
+
+fel_status fel_upload_mesh(fel_ctx* c, int inst, int dim, int64_t n_nodes, const double* xyz, int64_t n_elems,
+                           const int32_t* conn, const int8_t* shift, const double* box, const uint8_t* wall,
+                           const double* wall_normal) {
+    if (!c) return FEL_EINVAL;
+    if (c->bound) return fail(c, FEL_EINVAL, "upload after bind");
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
+    if (dim != c->lat.D) return fail(c, FEL_EINVAL, "dim %d does not match lattice D%dQ%d", dim, c->lat.D, c->lat.Q);
+    if (n_nodes <= 0 || n_elems <= 0 || !xyz || !conn) return fail(c, FEL_EINVAL, "empty mesh");
+    if (n_nodes > (int64_t)1 << 30) return fail(c, FEL_EINVAL, "too many nodes");
+    if (shift && !box) return fail(c, FEL_EINVAL, "shift given without box");
+    if (wall && !wall_normal) return fail(c, FEL_EINVAL, "wall flags given without normals");
+    const int nv = dim + 1;
+    for (int64_t i = 0; i < n_elems * nv; i++)
+        if (conn[i] < 0 || conn[i] >= n_nodes)
+            return fail(c, FEL_EINVAL, "element %lld vertex index %d out of range", (long long)(i / nv), conn[i]);
+    // renumber into the device order and assemble there
+    std::vector<int64_t> perm;
+    if (c->opt.node_order == FEL_ORDER_ZCURVE) {
+        perm = locality_order(dim, n_nodes, xyz);
+    } else {
+        perm.resize(n_nodes);
+        for (int64_t k = 0; k < n_nodes; k++) perm[k] = k;
+    }
+    std::vector<int32_t> inv(n_nodes);
+    for (int64_t k = 0; k < n_nodes; k++) inv[perm[k]] = (int32_t)k;
+    std::vector<double> pxyz(n_nodes * dim), pwn(wall ? n_nodes * dim : 0);
+    std::vector<uint8_t> pwall(wall ? n_nodes : 0);
+    for (int64_t k = 0; k < n_nodes; k++) {
+        const int64_t o = perm[k];
+        for (int r = 0; r < dim; r++) pxyz[k * dim + r] = xyz[o * dim + r];
+        if (wall) {
+            pwall[k] = wall[o];
+            for (int r = 0; r < dim; r++) pwn[k * dim + r] = wall_normal[o * dim + r];
+        }
+    }
+    std::vector<int32_t> pconn(n_elems * nv);
+    for (int64_t i = 0; i < n_elems * nv; i++) pconn[i] = inv[conn[i]];
+    return assemble(c, inst, dim, n_nodes, pxyz.data(), n_elems, pconn.data(), shift, box,
+                    wall ? pwall.data() : nullptr, wall ? pwn.data() : nullptr, std::move(perm));
 }
 
 static fel_status plan_layout(fel_ctx* c) {
@@ -588,14 +665,17 @@ hipError_t enqueue_solve(fel_ctx* c, int tb, int nt) {
     if (c->opt.mass_mode == FEL_MASS_LUMPED) {
         return timed(c, KC_LUMPED, [&] { return launch_lumped(L, tb, nt, s); });
     }
+    const int ni = c->ninst, np = c->NP;
+    auto fin = [&](int op) { return timed(c, KC_FINALIZE, [&] { return launch_finalize(L, 0, ni, op, np, s); }); };
     if ((e = timed(c, KC_CG_INIT, [&] { return launch_cg_init(L, tb, nt, s); })) != hipSuccess) return e;
+    if ((e = fin(0)) != hipSuccess) return e;
     for (int it = 0; it < c->cg_iters; it++) {
         const bool flip = (it & 1) != 0;
         if ((e = timed(c, KC_CG_A, [&] { return launch_cg_a(L, tb, nt, it == 0, flip, s); })) != hipSuccess)
             return e;
-        if ((e = timed(c, KC_CG_B, [&] { return launch_cg_b(L, tb, nt, it == c->cg_iters - 1, flip, s); })) !=
-            hipSuccess)
-            return e;
+        if ((e = fin(1)) != hipSuccess) return e;
+        if ((e = timed(c, KC_CG_B, [&] { return launch_cg_b(L, tb, nt, flip, s); })) != hipSuccess) return e;
+        if ((e = fin(it == c->cg_iters - 1 ? 3 : 2)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -664,7 +744,8 @@ fel_status fel_init_fields(fel_ctx* c, int inst, const fel_phys* ph, const doubl
     for (int r = 0; r < 3; r++) P.grav[r] = r < D ? ph->grav[r] : 0.0;
     P.beta = 12.0 * ph->sigma / (ph->xi * drho * drho * drho * drho);
     P.kappa = 1.5 * ph->xi * ph->sigma / (drho * drho);
-    P.scale = 1.0;
+    // deviation scale: FP16 deviations are stored times 2^8 (|deviation| up to ~250 fits)
+    P.scale = c->opt.precision == 2 ? 1.0 / 256.0 : 1.0;
     HIP_TRY(c, hipMemcpyAsync(c->dev + c->off.params + sizeof(InstParams) * inst, &P, sizeof(InstParams),
                               hipMemcpyHostToDevice, c->stream));
     const bool fp64 = c->opt.precision == 0;
@@ -672,7 +753,8 @@ fel_status fel_init_fields(fel_ctx* c, int inst, const fel_phys* ph, const doubl
     // upload rho, u, p into the field arrays at the instance rows
     auto put_field = [&](size_t off, int comp, const double* src, int stride) -> hipError_t {
         std::vector<double> v(N);
-        for (int64_t k = 0; k < N; k++) v[k] = src ? src[k * stride + comp] : 0.0;
+        const std::vector<int64_t>& perm = I.mesh.perm;
+        for (int64_t k = 0; k < N; k++) v[k] = src ? src[perm[k] * stride + comp] : 0.0;
         const size_t at = off + ((size_t)comp * R + P.row_begin) * (fp64 ? 8 : 4);
         if (fp64) {
             hipError_t e = hipMemcpyAsync(c->dev + at, v.data(), N * 8, hipMemcpyHostToDevice, c->stream);
@@ -749,17 +831,19 @@ fel_status fel_sync(fel_ctx* c) {
 namespace {
 
 // copy `count` rows of a device array of element size s (8 or 4) into doubles
-fel_status read_rows(fel_ctx* c, size_t off, int64_t first, int64_t count, double* out, int stride, int comp) {
+// (device rows first..first+count-1 land at caller indices perm[k])
+fel_status read_rows(fel_ctx* c, size_t off, int64_t first, int64_t count, double* out, int stride, int comp,
+                     const std::vector<int64_t>& perm) {
     const bool fp64 = c->opt.precision == 0;
     const size_t es = fp64 ? 8 : 4;
     if (fp64) {
         std::vector<double> v(count);
         HIP_TRY(c, hipMemcpy(v.data(), c->dev + off + first * es, count * es, hipMemcpyDeviceToHost));
-        for (int64_t k = 0; k < count; k++) out[k * stride + comp] = v[k];
+        for (int64_t k = 0; k < count; k++) out[perm[k] * stride + comp] = v[k];
     } else {
         std::vector<float> v(count);
         HIP_TRY(c, hipMemcpy(v.data(), c->dev + off + first * es, count * es, hipMemcpyDeviceToHost));
-        for (int64_t k = 0; k < count; k++) out[k * stride + comp] = v[k];
+        for (int64_t k = 0; k < count; k++) out[perm[k] * stride + comp] = v[k];
     }
     return FEL_OK;
 }
@@ -779,15 +863,16 @@ fel_status fel_read_fields(fel_ctx* c, int inst, double* rho, double* u, double*
     const int D = c->lat.D;
     const size_t R = c->R;
     fel_status st;
+    const std::vector<int64_t>& perm = I.mesh.perm;
     std::vector<double> r(N);
-    if ((st = read_rows(c, c->off.rho, rb, N, r.data(), 1, 0)) != FEL_OK) return st;
+    if ((st = read_rows(c, c->off.rho, rb, N, r.data(), 1, 0, perm)) != FEL_OK) return st;
     if (rho) std::copy(r.begin(), r.end(), rho);
     if (C)
         for (int64_t k = 0; k < N; k++) C[k] = (r[k] - I.phys.rho_v) / (I.phys.rho_l - I.phys.rho_v);
     if (u)
         for (int d = 0; d < D; d++)
-            if ((st = read_rows(c, c->off.u, (int64_t)d * R + rb, N, u, D, d)) != FEL_OK) return st;
-    if (p && (st = read_rows(c, c->off.p, rb, N, p, 1, 0)) != FEL_OK) return st;
+            if ((st = read_rows(c, c->off.u, (int64_t)d * R + rb, N, u, D, d, perm)) != FEL_OK) return st;
+    if (p && (st = read_rows(c, c->off.p, rb, N, p, 1, 0, perm)) != FEL_OK) return st;
     return FEL_OK;
 }
 
@@ -798,6 +883,7 @@ fel_status fel_conserved_sums(fel_ctx* c, int inst, double out[6]) {
     const InstParams& P = c->inst[inst].P;
     if (!c->inst[inst].have_phys) return fail(c, FEL_ESTATE, "instance %d not initialised", inst);
     HIP_TRY(c, launch_sums(c->L, P.tile_begin, P.tile_count, c->stream));
+    HIP_TRY(c, launch_finalize(c->L, inst, 1, 4, 8, c->stream));
     double v[8];
     HIP_TRY(c, hipMemcpyAsync(v, c->dev + c->off.sums + 64 * inst, 64, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -809,13 +895,42 @@ fel_status fel_get_state(fel_ctx* c, int inst, double* psibar) {
     if (!c || !psibar) return FEL_EINVAL;
     if (!c->bound) return fail(c, FEL_ESTATE, "get_state before bind");
     if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
-    if (c->opt.precision != 0) return fail(c, FEL_EINVAL, "state read-back for this precision not built yet");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const Instance& I = c->inst[inst];
-    const int64_t N = I.mesh.N;
-    for (int a = 0; a < 2 * c->opt.lattice; a++)
-        HIP_TRY(c, hipMemcpy(psibar + a * N, c->dev + c->off.psi + ((size_t)a * c->R + I.P.row_begin) * 8, N * 8,
+    const int64_t N = I.mesh.N, rb = I.P.row_begin;
+    const int Q = c->opt.lattice;
+    const size_t R = c->R;
+    std::vector<double> v(N);
+    if (c->opt.precision == 0) {
+        for (int a = 0; a < 2 * Q; a++) {
+            HIP_TRY(c, hipMemcpy(v.data(), c->dev + c->off.psi + ((size_t)a * R + rb) * 8, N * 8,
+                                 hipMemcpyDeviceToHost));
+            for (int64_t k = 0; k < N; k++) psibar[a * N + I.mesh.perm[k]] = v[k];
+        }
+        return FEL_OK;
+    }
+    // deviations: psi_a = w_a (ref + s d_a)
+    std::vector<float> ref(2 * N);
+    for (int h = 0; h < 2; h++)
+        HIP_TRY(c, hipMemcpy(ref.data() + h * N, c->dev + c->off.ref + ((size_t)h * R + rb) * 4, N * 4,
                              hipMemcpyDeviceToHost));
+    const bool half = c->opt.precision == 2;
+    std::vector<float> d(N);
+    std::vector<__half> dh(half ? N : 0);
+    for (int a = 0; a < 2 * Q; a++) {
+        if (half) {
+            HIP_TRY(c, hipMemcpy(dh.data(), c->dev + c->off.psi + ((size_t)a * R + rb) * 2, N * 2,
+                                 hipMemcpyDeviceToHost));
+            for (int64_t k = 0; k < N; k++) d[k] = __half2float(dh[k]);
+        } else {
+            HIP_TRY(c, hipMemcpy(d.data(), c->dev + c->off.psi + ((size_t)a * R + rb) * 4, N * 4,
+                                 hipMemcpyDeviceToHost));
+        }
+        const double w = c->lat.w[a % Q];
+        const float* rf = ref.data() + (a < Q ? 0 : N);
+        for (int64_t k = 0; k < N; k++)
+            psibar[a * N + I.mesh.perm[k]] = w * ((double)rf[k] + I.P.scale * (double)d[k]);
+    }
     return FEL_OK;
 }
 
@@ -824,12 +939,47 @@ fel_status fel_set_state(fel_ctx* c, int inst, const double* psibar) {
     if (!c->bound) return fail(c, FEL_ESTATE, "set_state before bind");
     if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
     if (!c->inst[inst].have_phys) return fail(c, FEL_ESTATE, "set_state needs init_fields first");
-    if (c->opt.precision != 0) return fail(c, FEL_EINVAL, "state upload for this precision not built yet");
     const Instance& I = c->inst[inst];
-    const int64_t N = I.mesh.N;
-    for (int a = 0; a < 2 * c->opt.lattice; a++)
-        HIP_TRY(c, hipMemcpy(c->dev + c->off.psi + ((size_t)a * c->R + I.P.row_begin) * 8, psibar + a * N, N * 8,
+    const int64_t N = I.mesh.N, rb = I.P.row_begin;
+    const int Q = c->opt.lattice;
+    const size_t R = c->R;
+    std::vector<double> v(N);
+    if (c->opt.precision == 0) {
+        for (int a = 0; a < 2 * Q; a++) {
+            for (int64_t k = 0; k < N; k++) v[k] = psibar[a * N + I.mesh.perm[k]];
+            HIP_TRY(c, hipMemcpy(c->dev + c->off.psi + ((size_t)a * R + rb) * 8, v.data(), N * 8,
+                                 hipMemcpyHostToDevice));
+        }
+        return FEL_OK;
+    }
+    // references: density and p / cs^2 (zeroth moments), deviations relative to them
+    std::vector<float> ref(2 * N, 0.0f);
+    for (int h = 0; h < 2; h++)
+        for (int64_t k = 0; k < N; k++) {
+            double sum = 0.0;
+            for (int a = 0; a < Q; a++) sum += psibar[(h * Q + a) * N + I.mesh.perm[k]];
+            ref[h * N + k] = (float)sum;
+        }
+    for (int h = 0; h < 2; h++)
+        HIP_TRY(c, hipMemcpy(c->dev + c->off.ref + ((size_t)h * R + rb) * 4, ref.data() + h * N, N * 4,
                              hipMemcpyHostToDevice));
+    const bool half = c->opt.precision == 2;
+    std::vector<float> d(N);
+    std::vector<__half> dh(half ? N : 0);
+    for (int a = 0; a < 2 * Q; a++) {
+        const double w = c->lat.w[a % Q];
+        const float* rf = ref.data() + (a < Q ? 0 : N);
+        for (int64_t k = 0; k < N; k++)
+            d[k] = (float)((psibar[a * N + I.mesh.perm[k]] / w - (double)rf[k]) / I.P.scale);
+        if (half) {
+            for (int64_t k = 0; k < N; k++) dh[k] = __float2half(d[k]);
+            HIP_TRY(c, hipMemcpy(c->dev + c->off.psi + ((size_t)a * R + rb) * 2, dh.data(), N * 2,
+                                 hipMemcpyHostToDevice));
+        } else {
+            HIP_TRY(c, hipMemcpy(c->dev + c->off.psi + ((size_t)a * R + rb) * 4, d.data(), N * 4,
+                                 hipMemcpyHostToDevice));
+        }
+    }
     return FEL_OK;
 }
 
@@ -842,15 +992,16 @@ fel_status fel_read_aux(fel_ctx* c, int inst, int which, double* out) {
     const int64_t N = I.mesh.N, rb = I.P.row_begin;
     const int D = c->lat.D, Q = c->opt.lattice;
     const size_t R = c->R;
+    const std::vector<int64_t>& perm = I.mesh.perm;
     fel_status st = FEL_OK;
     switch (which) {
     case FEL_AUX_GRADRHO:
-        for (int d = 0; d < D && st == FEL_OK; d++) st = read_rows(c, c->off.grad, (int64_t)d * R + rb, N, out, D, d);
+        for (int d = 0; d < D && st == FEL_OK; d++) st = read_rows(c, c->off.grad, (int64_t)d * R + rb, N, out, D, d, perm);
         return st;
     case FEL_AUX_MU:
-        return read_rows(c, c->off.mu, rb, N, out, 1, 0);
+        return read_rows(c, c->off.mu, rb, N, out, 1, 0, perm);
     case FEL_AUX_S:
-        for (int d = 0; d < D && st == FEL_OK; d++) st = read_rows(c, c->off.S, (int64_t)d * R + rb, N, out, D, d);
+        for (int d = 0; d < D && st == FEL_OK; d++) st = read_rows(c, c->off.S, (int64_t)d * R + rb, N, out, D, d, perm);
         return st;
     case FEL_AUX_DELTA:
         for (int64_t k = 0; k < N; k++) {
@@ -859,7 +1010,7 @@ fel_status fel_read_aux(fel_ctx* c, int inst, int which, double* out) {
         }
         for (int j = 0; j < c->NP && st == FEL_OK; j++) {
             const int pop = j < Q - 1 ? j + 1 : Q + (j - (Q - 1)) + 1;
-            st = read_rows(c, c->off.X, (int64_t)j * R + rb, N, out + pop * N, 1, 0);
+            st = read_rows(c, c->off.X, (int64_t)j * R + rb, N, out + pop * N, 1, 0, perm);
         }
         return st;
     default:

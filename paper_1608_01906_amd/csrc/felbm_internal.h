@@ -80,6 +80,7 @@ enum KernelClass {
     KC_COLLIDE,
     KC_INIT,
     KC_SUMS,
+    KC_FINALIZE,
     KC_COUNT
 };
 
@@ -90,7 +91,9 @@ const char* kernel_class_name(int k);
 hipError_t launch_stream(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, bool flip, hipStream_t s);
-hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool last, bool flip, hipStream_t s);
+hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool flip, hipStream_t s);
+// op: 0 CG init, 1 alpha, 2 beta, 3 final residual check, 4 conserved sums; np values per tile
+hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int np, hipStream_t s);
 hipError_t launch_lumped(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_moments(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_grad(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);

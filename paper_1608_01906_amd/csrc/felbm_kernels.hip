@@ -9,9 +9,9 @@
 // fetched by the same XCD's L2.
 //
 // Reductions (CG dot products, conserved sums) are FP64: per-tile partials
-// in a fixed order (wavefront shuffles, then LDS), and the last block of
-// each instance to finish sums that instance's partials in a fixed order,
-// so results are bitwise reproducible and no extra launch is needed.
+// in a fixed order (wavefront shuffles, then LDS), then one small finalize
+// launch per instance sums the partials in a fixed order, so results are
+// bitwise reproducible.
 #include "felbm_internal.h"
 
 namespace fel {
@@ -56,7 +56,7 @@ template <> struct Lat<19> {
 
 const char* kernel_class_name(int k) {
     static const char* names[KC_COUNT] = {"stream", "cg_init", "cg_a", "cg_b", "lumped", "moments",
-                                          "grad", "div", "collide", "init", "sums"};
+                                          "grad", "div", "collide", "init", "sums", "finalize"};
     return (k >= 0 && k < KC_COUNT) ? names[k] : "?";
 }
 
@@ -85,53 +85,93 @@ template <typename T> __device__ __forceinline__ void st(void* p, int64_t i, T v
     reinterpret_cast<T*>(p)[i] = v;
 }
 
-// Per-tile partial sums of NP values, then the instance's last block sums
-// all its tiles (fixed order) and calls op(inst, j, total) for j < NP.
-template <int NP, typename Op>
-__device__ __forceinline__ void reduce_finalize(const DevLayout& L, int tile, int inst, double (&part)[NP],
-                                                Op op) {
+// Deterministic FP64 reduction of NP values per tile: add(j, v) reduces
+// v over the wavefront (shuffles) into LDS; finish() sums the waves in a
+// fixed order and stores the tile's partials with plain stores.  The
+// instance totals are formed by k_finalize in the next launch, so no
+// kernel needs a device-scope fence (on multi-XCD parts such a fence writes
+// back and invalidates the XCD's L2, which would discard the neighbour
+// reuse the gathers depend on).
+template <int NP>
+struct TileReducer {
     static_assert(NP <= TILE, "too many reduction values");
-    __shared__ double lds[TILE / 64][NP];
-    __shared__ double fin[TILE];
-    __shared__ int s_last;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double (*lds)[NP];
+    __device__ __forceinline__ explicit TileReducer(double (*buf)[NP]) : lds(buf) {}
+    __device__ __forceinline__ void add(int j, double v) {
+        v = wave_sum(v);
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6][j] = v;
+    }
+    __device__ __forceinline__ void finish(const DevLayout& L, int tile) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < NP; j += TILE) {
+            double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < NP; j++) {
-        const double v = wave_sum(part[j]);
-        if (lane == 0) lds[wave][j] = v;
+            for (int w = 0; w < TILE / 64; w++) s += lds[w][j];
+            L.partial[(int64_t)tile * NP + j] = s;
+        }
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < NP; j += TILE) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < TILE / 64; w++) s += lds[w][j];
-        L.partial[(int64_t)tile * NP + j] = s;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int prev = atomicAdd(&L.counter[inst], 1);
-        s_last = (prev == L.params[inst].tile_count - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+};
+
+// What a finalize launch does with the instance totals.
+enum FinOp { FIN_CG_INIT = 0, FIN_CG_A, FIN_CG_B, FIN_CG_LAST, FIN_SUMS };
+
+// One block per instance: sums the instance's tile partials in a fixed
+// order and derives the CG scalars (or stores the conserved sums).
+constexpr int FIN_THREADS = 1024;
+
+template <int NP>
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(DevLayout L, int inst_begin, int op) {
+    __shared__ double fin[FIN_THREADS];
+    const int inst = inst_begin + blockIdx.x;
     const int tb = L.params[inst].tile_begin, nt = L.params[inst].tile_count;
-    constexpr int G = TILE / NP;
+    constexpr int G = FIN_THREADS / NP;
     const int j = threadIdx.x % NP, g = threadIdx.x / NP;
     double s = 0.0;
-    if (g < G)
-        for (int t = g; t < nt; t += G)
-            s += __hip_atomic_load(&L.partial[(int64_t)(tb + t) * NP + j], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+    if (g < G) {
+        const double* src = L.partial + (int64_t)tb * NP + j;
+#pragma unroll 16
+        for (int t = g; t < nt; t += G) s += src[(int64_t)t * NP];
+    }
     fin[threadIdx.x] = s;
     __syncthreads();
-    if (threadIdx.x < NP) {
-        double tot = 0.0;
-        for (int gg = 0; gg < G; gg++) tot += fin[gg * NP + threadIdx.x];
-        op(inst, (int)threadIdx.x, tot);
+    if (threadIdx.x >= NP) return;
+    double tot = 0.0;
+    for (int gg = 0; gg < G; gg++) tot += fin[gg * NP + threadIdx.x];
+    const int i = inst * NP + j;
+    switch (op) {
+    case FIN_CG_INIT:
+        L.rz[i] = tot;
+        L.rz0[i] = tot;
+        L.beta[i] = 0.0;
+        break;
+    case FIN_CG_A:
+        L.alpha[i] = (tot != 0.0) ? L.rz[i] / tot : 0.0;
+        break;
+    case FIN_CG_B: {
+        const double rz = L.rz[i];
+        L.beta[i] = (rz != 0.0) ? tot / rz : 0.0;
+        L.rz[i] = tot;
+        break;
     }
-    if (threadIdx.x == 0) atomicExch(&L.counter[inst], 0);
+    case FIN_CG_LAST: {
+        const double r0 = L.rz0[i];
+        if (r0 > 0.0 && !(tot <= L.cg_tol2 * r0)) atomicOr(L.status, 2u);
+        break;
+    }
+    case FIN_SUMS:
+        L.sums[inst * 8 + j] = tot;
+        break;
+    }
+}
+
+#define FEL_REDUCER(NAME, NP)                         \
+    __shared__ double NAME##_buf[TILE / 64][NP];      \
+    TileReducer<NP> NAME(NAME##_buf)
+
+// gathers through a uniform base and a 32-bit byte offset
+template <typename T>
+__device__ __forceinline__ T gat(const T* base, int idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)idx * (uint32_t)sizeof(T));
 }
 
 // ---------------------------------------------------------------------------
@@ -186,36 +226,32 @@ __global__ __launch_bounds__(TILE) void k_cg_init(DevLayout L, int tile_begin) {
     const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
     const int inst = L.tile_inst[tile];
     const int64_t R = L.R;
-    const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+    const int row = tile * TILE + threadIdx.x;
     const T* rhs = reinterpret_cast<const T*>(L.Pb);
     const T* minv = reinterpret_cast<const T*>(L.minv);
-    int64_t c[W];
+    int c[W];
     T mv[W], mi[W];
 #pragma unroll
     for (int k = 0; k < W; k++) {
         c[k] = L.col[k * R + row];
         mv[k] = ld<T>(L.Mval, k * R + row);
-        mi[k] = minv[c[k]];
+        mi[k] = gat(minv, c[k]);
     }
     const T mrow = minv[row];
-    double part[NP];
-#pragma unroll
+    FEL_REDUCER(red, NP);
+#pragma unroll 2
     for (int j = 0; j < NP; j++) {
         const T* b = rhs + (int64_t)j * R;
         T acc = 0;
 #pragma unroll
-        for (int k = 0; k < W; k++) acc += mv[k] * (b[c[k]] * mi[k]);
-        const T bj = b[row];
+        for (int k = 0; k < W; k++) acc += mv[k] * (gat(b, c[k]) * mi[k]);
+        const T bj = gat(b, row);
         const T r = bj - acc;
         st<T>(L.X, (int64_t)j * R + row, bj * mrow);
         st<T>(L.Rv, (int64_t)j * R + row, r);
-        part[j] = (double)r * (double)r * (double)mrow;
+        red.add(j, (double)r * (double)r * (double)mrow);
     }
-    reduce_finalize<NP>(L, tile, inst, part, [&](int in, int j, double tot) {
-        L.rz[in * NP + j] = tot;
-        L.rz0[in * NP + j] = tot;
-        L.beta[in * NP + j] = 0.0;
-    });
+    red.finish(L, tile);
 }
 
 // p_new = r / m + beta p_old (p_old unread on the first iteration),
@@ -225,58 +261,61 @@ __global__ __launch_bounds__(TILE) void k_cg_a(DevLayout L, int tile_begin, int 
     const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
     const int inst = L.tile_inst[tile];
     const int64_t R = L.R;
-    const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+    const int row = tile * TILE + threadIdx.x;
     const T* Rv = reinterpret_cast<const T*>(L.Rv);
     const T* Pold = reinterpret_cast<const T*>(flip ? L.Pa : L.Pb);
     T* Pnew = reinterpret_cast<T*>(flip ? L.Pb : L.Pa);
     const T* minv = reinterpret_cast<const T*>(L.minv);
-    int64_t c[W];
+    int c[W];
     T mv[W], mi[W];
 #pragma unroll
     for (int k = 0; k < W; k++) {
         c[k] = L.col[k * R + row];
         mv[k] = ld<T>(L.Mval, k * R + row);
-        mi[k] = minv[c[k]];
+        mi[k] = gat(minv, c[k]);
     }
     const T mrow = minv[row];
-    double part[NP];
+    FEL_REDUCER(red, NP);
+    if (first) {
+#pragma unroll 2
+        for (int j = 0; j < NP; j++) {
+            const T* r = Rv + (int64_t)j * R;
+            T acc = 0;
 #pragma unroll
-    for (int j = 0; j < NP; j++) {
-        const T* r = Rv + (int64_t)j * R;
-        const T* po = Pold + (int64_t)j * R;
-        T acc = 0, pown;
-        if (first) {
-#pragma unroll
-            for (int k = 0; k < W; k++) acc += mv[k] * (r[c[k]] * mi[k]);
-            pown = r[row] * mrow;
-        } else {
-            const T bet = (T)L.beta[inst * NP + j];
-#pragma unroll
-            for (int k = 0; k < W; k++) acc += mv[k] * (r[c[k]] * mi[k] + bet * po[c[k]]);
-            pown = r[row] * mrow + bet * po[row];
+            for (int k = 0; k < W; k++) acc += mv[k] * (gat(r, c[k]) * mi[k]);
+            const T pown = gat(r, row) * mrow;
+            Pnew[(int64_t)j * R + row] = pown;
+            red.add(j, (double)pown * (double)acc);
         }
-        Pnew[(int64_t)j * R + row] = pown;
-        part[j] = (double)pown * (double)acc;
+    } else {
+#pragma unroll 2
+        for (int j = 0; j < NP; j++) {
+            const T* r = Rv + (int64_t)j * R;
+            const T* po = Pold + (int64_t)j * R;
+            const T bet = (T)L.beta[inst * NP + j];
+            T acc = 0;
+#pragma unroll
+            for (int k = 0; k < W; k++) acc += mv[k] * (gat(r, c[k]) * mi[k] + bet * gat(po, c[k]));
+            const T pown = gat(r, row) * mrow + bet * gat(po, row);
+            Pnew[(int64_t)j * R + row] = pown;
+            red.add(j, (double)pown * (double)acc);
+        }
     }
-    reduce_finalize<NP>(L, tile, inst, part, [&](int in, int j, double tot) {
-        const double rz = L.rz[in * NP + j];
-        L.alpha[in * NP + j] = (tot != 0.0) ? rz / tot : 0.0;
-    });
+    red.finish(L, tile);
 }
 
 // x += alpha p, r -= alpha M p (M p recomputed), reduces r.z -> beta;
-// on the last iteration checks r.z / r0.z0 against the tolerance instead.
 template <typename T, int W, int NP>
-__global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int last, int flip) {
+__global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int flip) {
     const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
     const int inst = L.tile_inst[tile];
     const int64_t R = L.R;
-    const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+    const int row = tile * TILE + threadIdx.x;
     const T* Pn = reinterpret_cast<const T*>(flip ? L.Pb : L.Pa);
     T* X = reinterpret_cast<T*>(L.X);
     T* Rv = reinterpret_cast<T*>(L.Rv);
     const T* minv = reinterpret_cast<const T*>(L.minv);
-    int64_t c[W];
+    int c[W];
     T mv[W];
 #pragma unroll
     for (int k = 0; k < W; k++) {
@@ -284,33 +323,22 @@ __global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int 
         mv[k] = ld<T>(L.Mval, k * R + row);
     }
     const T mrow = minv[row];
-    double part[NP];
-#pragma unroll
+    FEL_REDUCER(red, NP);
+#pragma unroll 2
     for (int j = 0; j < NP; j++) {
         const T* p = Pn + (int64_t)j * R;
         T q = 0;
 #pragma unroll
-        for (int k = 0; k < W; k++) q += mv[k] * p[c[k]];
+        for (int k = 0; k < W; k++) q += mv[k] * gat(p, c[k]);
         const T al = (T)L.alpha[inst * NP + j];
         const int64_t i = (int64_t)j * R + row;
-        const T x = X[i] + al * p[row];
+        const T x = X[i] + al * gat(p, row);
         const T r = Rv[i] - al * q;
         X[i] = x;
         Rv[i] = r;
-        part[j] = (double)r * (double)r * (double)mrow;
+        red.add(j, (double)r * (double)r * (double)mrow);
     }
-    if (last) {
-        reduce_finalize<NP>(L, tile, inst, part, [&](int in, int j, double tot) {
-            const double r0 = L.rz0[in * NP + j];
-            if (r0 > 0.0 && !(tot <= L.cg_tol2 * r0)) atomicOr(L.status, 2u);
-        });
-    } else {
-        reduce_finalize<NP>(L, tile, inst, part, [&](int in, int j, double tot) {
-            const double rz = L.rz[in * NP + j];
-            L.beta[in * NP + j] = (rz != 0.0) ? tot / rz : 0.0;
-            L.rz[in * NP + j] = tot;
-        });
-    }
+    red.finish(L, tile);
 }
 
 // lumped-mass approximation: Delta = rhs / m
@@ -620,7 +648,309 @@ __global__ __launch_bounds__(TILE) void k_sums_plain(DevLayout L, int tile_begin
         for (int r = 0; r < D; r++) part[3 + r] = m * mom[r];
     }
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(L.status, 1u);
-    reduce_finalize<8>(L, tile, inst, part, [&](int in, int j, double tot) { L.sums[in * 8 + j] = tot; });
+    FEL_REDUCER(red, 8);
+#pragma unroll
+    for (int j = 0; j < 8; j++) red.add(j, part[j]);
+    red.finish(L, tile);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 path: populations stored as scaled deviations from a node reference,
+//   f_a = w_a (ref_f + s d_a),   g_a = w_a (ref_g + s d_{Q+a}),
+// with ref_f the density and ref_g = p / cs^2 of the last collision and s
+// a per-instance power of two.  Every FP32 operation below acts on small
+// quantities: the streaming operator on differences to the row's own value
+// (each row of dt C + dt^2 D sums to zero), the collision on deviations from
+// the new reference.
+
+template <typename S> __device__ __forceinline__ float ldS(const void* p, int64_t i) {
+    return (float)reinterpret_cast<const S*>(p)[i];
+}
+template <typename S> __device__ __forceinline__ void stS(void* p, int64_t i, float v) {
+    reinterpret_cast<S*>(p)[i] = (S)v;
+}
+
+template <int Q, int W, typename S>
+__global__ __launch_bounds__(TILE) void k_stream_dev(DevLayout L, int tile_begin) {
+    using LT = Lat<Q>;
+    constexpr int D = LT::D, NB = LT::NB, NP = 2 * (Q - 1);
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    const int64_t R = L.R;
+    const int row = tile * TILE + threadIdx.x;
+    const InstParams& P = L.params[L.tile_inst[tile]];
+    const float dt = (float)P.dt, h2 = 0.5f * dt * dt, sc = (float)P.scale;
+    const float* B = reinterpret_cast<const float*>(L.basis);
+    const float* reff = L.ref;
+    const float* refg = L.ref + R;
+    const float rf0 = reff[row], rg0 = refg[row];
+    float d0[NP];
+#pragma unroll
+    for (int a = 1; a < Q; a++) {
+        d0[a - 1] = ldS<S>(L.psi, (int64_t)a * R + row);
+        d0[Q - 1 + a - 1] = ldS<S>(L.psi, (int64_t)(Q + a) * R + row);
+    }
+    float acc[NP];
+#pragma unroll
+    for (int j = 0; j < NP; j++) acc[j] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+        const int c = L.col[k * R + row];
+        float b[NB];
+#pragma unroll
+        for (int n = 0; n < NB; n++) b[n] = B[((int64_t)n * W + k) * R + row];
+        const float drf = gat(reff, c) - rf0, drg = gat(refg, c) - rg0;
+#pragma unroll
+        for (int a = 1; a < Q; a++) {
+            const float ex = LT::e(a, 0), ey = LT::e(a, 1), ez = LT::e(a, 2);
+            float coef;
+            if constexpr (D == 2) {
+                coef = dt * (ex * b[0] + ey * b[1]) + h2 * (ex * ex * b[2] + ey * ey * b[3] + ex * ey * b[4]);
+            } else {
+                coef = dt * (ex * b[0] + ey * b[1] + ez * b[2]) +
+                       h2 * (ex * ex * b[3] + ey * ey * b[4] + ez * ez * b[5] + ex * ey * b[6] +
+                             ex * ez * b[7] + ey * ez * b[8]);
+            }
+            const float df = ldS<S>(L.psi, (int64_t)a * R + c) - d0[a - 1];
+            const float dg = ldS<S>(L.psi, (int64_t)(Q + a) * R + c) - d0[Q - 1 + a - 1];
+            acc[a - 1] += coef * (drf + sc * df);
+            acc[Q - 1 + a - 1] += coef * (drg + sc * dg);
+        }
+    }
+    float* rhs = reinterpret_cast<float*>(L.Pb);
+#pragma unroll
+    for (int a = 1; a < Q; a++) {
+        const float w = (float)LT::w(a);
+        rhs[(int64_t)(a - 1) * R + row] = -w * acc[a - 1];
+        rhs[(int64_t)(Q - 1 + a - 1) * R + row] = -w * acc[Q - 1 + a - 1];
+    }
+}
+
+// streamed deviations e_a = s d_a + Delta_a / w_a of one distribution
+// (base 0: f, base Q: g), walls applied: psi_s,a = w_a (ref + e_a)
+template <int Q, typename S>
+__device__ __forceinline__ void streamed_dev(const DevLayout& L, int row, int base, float sc, float (&e)[Q]) {
+    using LT = Lat<Q>;
+    const int64_t R = L.R;
+    const float* X = reinterpret_cast<const float*>(L.X);
+    const int xb = base ? (Q - 1) : 0;
+    e[0] = sc * ldS<S>(L.psi, (int64_t)base * R + row);
+#pragma unroll
+    for (int a = 1; a < Q; a++)
+        e[a] = sc * ldS<S>(L.psi, (int64_t)(base + a) * R + row) +
+               X[(int64_t)(xb + a - 1) * R + row] * (float)(1.0 / LT::w(a));
+}
+
+template <int Q, typename S>
+__global__ __launch_bounds__(TILE) void k_moments_dev(DevLayout L, int tile_begin) {
+    using LT = Lat<Q>;
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    const int row = tile * TILE + threadIdx.x;
+    const InstParams& P = L.params[L.tile_inst[tile]];
+    float e[Q];
+    streamed_dev<Q, S>(L, row, 0, (float)P.scale, e);
+    bounce<Q>(L.wmask[row], e);
+    float drho = 0.0f;
+#pragma unroll
+    for (int a = 0; a < Q; a++) drho += (float)LT::w(a) * e[a];
+    st<float>(L.rho, row, L.ref[row] + drho);
+}
+
+template <int W, int D, typename T>
+__device__ __forceinline__ void gather_grad_of(const DevLayout& L, const void* field, int row, T (&gm)[3]) {
+    const int64_t R = L.R;
+    const T* f = reinterpret_cast<const T*>(field);
+    const T* B = reinterpret_cast<const T*>(L.basis);
+#pragma unroll
+    for (int r = 0; r < 3; r++) gm[r] = 0;
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+        const T v = gat(f, L.col[k * R + row]);
+#pragma unroll
+        for (int r = 0; r < D; r++) gm[r] += B[((int64_t)r * W + k) * R + row] * v;
+    }
+    const T mi = ld<T>(L.minv, row);
+#pragma unroll
+    for (int r = 0; r < D; r++) gm[r] *= mi;
+}
+
+// Per-direction deviation terms at one node, all divided by w_a:
+//   gh   = Gamma_a(u) / w_a - 1
+//   F    = F_a / w_a,  G = (G_a + body force) / w_a
+struct NodeF {
+    float rho, P, u[3], gr[3], S[3], gm[3], g[3], dt;
+};
+
+template <int Q, typename Fn>
+__device__ __forceinline__ void node_terms_dev(const NodeF& n, Fn fn) {
+    using LT = Lat<Q>;
+    constexpr int D = LT::D;
+    float uu = 0.0f, u2[3], uu2 = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        uu += n.u[r] * n.u[r];
+        u2[r] = n.u[r] + n.g[r] * n.dt;
+        uu2 += u2[r] * u2[r];
+    }
+    const float hdt = 0.5f * n.dt;
+#pragma unroll
+    for (int a = 0; a < Q; a++) {
+        float eu = 0.0f, eu2 = 0.0f, ef = 0.0f, eg = 0.0f, eS = 0.0f;
+#pragma unroll
+        for (int r = 0; r < D; r++) {
+            const float e = (float)LT::e(a, r);
+            const float em = e - n.u[r];
+            eu += e * n.u[r];
+            eu2 += e * u2[r];
+            ef += em * (n.gr[r] * (1.0f / 3.0f) - n.rho * n.gm[r]);
+            eg += em * n.gr[r];
+            eS += em * n.S[r];
+        }
+        const float gh = 3.0f * eu + 4.5f * eu * eu - 1.5f * uu;
+        const float gh2 = 3.0f * eu2 + 4.5f * eu2 * eu2 - 1.5f * uu2;
+        const float F = hdt * 3.0f * ef * (1.0f + gh);
+        const float G = hdt * eg * gh + hdt * 3.0f * eS * (1.0f + gh) + 0.5f * n.rho * (gh2 - gh);
+        fn(a, gh, F, G);
+    }
+}
+
+__device__ __forceinline__ float tau_of_f(const InstParams& P, float rho) {
+    float C = (rho - (float)P.rho_v) / (float)(P.rho_l - P.rho_v);
+    C = fminf(fmaxf(C, 0.0f), 1.0f);
+    return 1.0f / (C / (float)P.tau_l + (1.0f - C) / (float)P.tau_v);
+}
+
+template <int Q, int W, typename S>
+__global__ __launch_bounds__(TILE) void k_collide_dev(DevLayout L, int tile_begin) {
+    using LT = Lat<Q>;
+    constexpr int D = LT::D;
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    const int64_t R = L.R;
+    const int row = tile * TILE + threadIdx.x;
+    const InstParams& P = L.params[L.tile_inst[tile]];
+    if (row >= P.row_end) return;
+    const float sc = (float)P.scale, isc = 1.0f / sc;
+    float ef[Q], eg[Q];
+    streamed_dev<Q, S>(L, row, 0, sc, ef);
+    streamed_dev<Q, S>(L, row, Q, sc, eg);
+    const uint32_t mask = L.wmask[row];
+    bounce<Q>(mask, ef);
+    bounce<Q>(mask, eg);
+    NodeF n;
+    n.dt = (float)P.dt;
+    const float reff = L.ref[row], refg = L.ref[R + row];
+    n.rho = ld<float>(L.rho, row);            // = reff + sum_a w_a ef_a
+    float dg = 0.0f, mom[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int a = 0; a < Q; a++) {
+        const float we = (float)LT::w(a) * eg[a];
+        dg += we;
+#pragma unroll
+        for (int r = 0; r < D; r++) mom[r] += (float)LT::e(a, r) * we;
+    }
+    float ugr = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        n.g[r] = (r < D) ? (float)P.grav[r] : 0.0f;
+        n.gr[r] = (r < D) ? ld<float>(L.grad, (int64_t)r * R + row) : 0.0f;
+        n.S[r] = (r < D) ? ld<float>(L.S, (int64_t)r * R + row) : 0.0f;
+        n.u[r] = (r < D) ? (mom[r] + 0.5f * n.dt * n.S[r] + 0.5f * n.dt * n.rho * n.g[r]) / n.rho : 0.0f;
+        ugr += n.u[r] * n.gr[r];
+    }
+    n.P = refg + (dg + 0.5f * n.dt * ugr);    // p / cs^2
+    gather_grad_of<W, D, float>(L, L.mu, row, n.gm);
+    const float tau = tau_of_f(P, n.rho);
+    const float om = 2.0f / (2.0f * tau + 1.0f), ph = 4.0f * tau / (2.0f * tau + 1.0f);
+    const float d_rf = reff - n.rho, d_rg = refg - n.P;   // old minus new reference (exact)
+    bool bad = false;
+    node_terms_dev<Q>(n, [&](int a, float gh, float F, float G) {
+        const float eqd = n.rho * gh;                    // f_eq / w - rho  and  g_eq / w - p / cs^2
+        const float Ef = d_rf + ef[a], Eg = d_rg + eg[a];
+        const float fn = Ef - om * (Ef - eqd) + ph * F;
+        const float gn = Eg - om * (Eg - eqd) + ph * G;
+        bad |= !isfinite(fn) || !isfinite(gn);
+        stS<S>(L.psi, (int64_t)a * R + row, fn * isc);
+        stS<S>(L.psi, (int64_t)(Q + a) * R + row, gn * isc);
+    });
+    L.ref[row] = n.rho;
+    L.ref[R + row] = n.P;
+#pragma unroll
+    for (int r = 0; r < D; r++) st<float>(L.u, (int64_t)r * R + row, n.u[r]);
+    st<float>(L.p, row, n.P * (1.0f / 3.0f));
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(L.status, 1u);
+}
+
+template <int Q, int W, typename S>
+__global__ __launch_bounds__(TILE) void k_init_dev(DevLayout L, int tile_begin) {
+    using LT = Lat<Q>;
+    constexpr int D = LT::D;
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    const int64_t R = L.R;
+    const int row = tile * TILE + threadIdx.x;
+    const InstParams& P = L.params[L.tile_inst[tile]];
+    if (row >= P.row_end) {
+#pragma unroll
+        for (int a = 0; a < 2 * Q; a++) stS<S>(L.psi, (int64_t)a * R + row, 0.0f);
+        L.ref[row] = 0.0f;
+        L.ref[R + row] = 0.0f;
+        return;
+    }
+    NodeF n;
+    n.dt = (float)P.dt;
+    n.rho = ld<float>(L.rho, row);
+    n.P = 3.0f * ld<float>(L.p, row);
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        n.g[r] = (r < D) ? (float)P.grav[r] : 0.0f;
+        n.gr[r] = (r < D) ? ld<float>(L.grad, (int64_t)r * R + row) : 0.0f;
+        n.S[r] = (r < D) ? ld<float>(L.S, (int64_t)r * R + row) : 0.0f;
+        n.u[r] = (r < D) ? ld<float>(L.u, (int64_t)r * R + row) : 0.0f;
+    }
+    gather_grad_of<W, D, float>(L, L.mu, row, n.gm);
+    const float isc = 1.0f / (float)P.scale;
+    node_terms_dev<Q>(n, [&](int a, float gh, float F, float G) {
+        stS<S>(L.psi, (int64_t)a * R + row, (n.rho * gh + F) * isc);
+        stS<S>(L.psi, (int64_t)(Q + a) * R + row, (n.rho * gh + G) * isc);
+    });
+    L.ref[row] = n.rho;
+    L.ref[R + row] = n.P;
+}
+
+template <int Q, typename S>
+__global__ __launch_bounds__(TILE) void k_sums_dev(DevLayout L, int tile_begin) {
+    using LT = Lat<Q>;
+    constexpr int D = LT::D;
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    const int inst = L.tile_inst[tile];
+    const int64_t R = L.R;
+    const int row = tile * TILE + threadIdx.x;
+    const InstParams& P = L.params[inst];
+    const double m = L.mlump[row];
+    double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool bad = false;
+    if (row < P.row_end) {
+        const double sc = P.scale;
+        double drho = 0.0, mom[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < Q; a++) {
+            const double fa = ldS<S>(L.psi, (int64_t)a * R + row), ga = ldS<S>(L.psi, (int64_t)(Q + a) * R + row);
+            bad |= !isfinite(fa) || !isfinite(ga);
+            drho += LT::w(a) * sc * fa;
+#pragma unroll
+            for (int r = 0; r < D; r++) mom[r] += LT::e(a, r) * LT::w(a) * sc * ga;
+        }
+        const double rho = (double)L.ref[row] + drho;
+        const double C = (rho - P.rho_v) / (P.rho_l - P.rho_v);
+        part[0] = m * rho;
+        part[1] = m * C;
+        part[2] = m * (1.0 - C);
+#pragma unroll
+        for (int r = 0; r < D; r++) part[3 + r] = m * mom[r];
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(L.status, 1u);
+    FEL_REDUCER(red, 8);
+#pragma unroll
+    for (int j = 0; j < 8; j++) red.add(j, part[j]);
+    red.finish(L, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -643,11 +973,13 @@ static hipError_t dispatch_qw(const DevLayout& L, A... args) {
 
 template <int Q, int W> struct StreamBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
-        if (L.precision == 0) {
+        if (L.precision == 0)
             hipLaunchKernelGGL((k_stream_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
-            FEL_CHECK_LAUNCH();
-        }
-        return hipErrorInvalidValue;
+        else if (L.precision == 1)
+            hipLaunchKernelGGL((k_stream_dev<Q, W, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        else
+            hipLaunchKernelGGL((k_stream_dev<Q, W, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct CgInitBody {
@@ -671,12 +1003,12 @@ template <int Q, int W> struct CgABody {
     }
 };
 template <int Q, int W> struct CgBBody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, bool last, bool flip, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, bool flip, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_cg_b<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)last, (int)flip);
+            hipLaunchKernelGGL((k_cg_b<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)flip);
         else
-            hipLaunchKernelGGL((k_cg_b<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)last, (int)flip);
+            hipLaunchKernelGGL((k_cg_b<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)flip);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -692,11 +1024,13 @@ template <int Q, int W> struct LumpedBody {
 };
 template <int Q, int W> struct MomentsBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
-        if (L.precision == 0) {
+        if (L.precision == 0)
             hipLaunchKernelGGL((k_moments_plain<Q>), dim3(nt), dim3(TILE), 0, s, L, tb);
-            FEL_CHECK_LAUNCH();
-        }
-        return hipErrorInvalidValue;
+        else if (L.precision == 1)
+            hipLaunchKernelGGL((k_moments_dev<Q, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        else
+            hipLaunchKernelGGL((k_moments_dev<Q, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct GradBody {
@@ -721,29 +1055,35 @@ template <int Q, int W> struct DivBody {
 };
 template <int Q, int W> struct CollideBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
-        if (L.precision == 0) {
+        if (L.precision == 0)
             hipLaunchKernelGGL((k_collide_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
-            FEL_CHECK_LAUNCH();
-        }
-        return hipErrorInvalidValue;
+        else if (L.precision == 1)
+            hipLaunchKernelGGL((k_collide_dev<Q, W, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        else
+            hipLaunchKernelGGL((k_collide_dev<Q, W, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct InitBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
-        if (L.precision == 0) {
+        if (L.precision == 0)
             hipLaunchKernelGGL((k_init_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
-            FEL_CHECK_LAUNCH();
-        }
-        return hipErrorInvalidValue;
+        else if (L.precision == 1)
+            hipLaunchKernelGGL((k_init_dev<Q, W, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        else
+            hipLaunchKernelGGL((k_init_dev<Q, W, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct SumsBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
-        if (L.precision == 0) {
+        if (L.precision == 0)
             hipLaunchKernelGGL((k_sums_plain<Q>), dim3(nt), dim3(TILE), 0, s, L, tb);
-            FEL_CHECK_LAUNCH();
-        }
-        return hipErrorInvalidValue;
+        else if (L.precision == 1)
+            hipLaunchKernelGGL((k_sums_dev<Q, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        else
+            hipLaunchKernelGGL((k_sums_dev<Q, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        FEL_CHECK_LAUNCH();
     }
 };
 
@@ -756,8 +1096,19 @@ hipError_t launch_cg_init(const DevLayout& L, int tb, int nt, hipStream_t s) {
 hipError_t launch_cg_a(const DevLayout& L, int tb, int nt, bool first, bool flip, hipStream_t s) {
     return dispatch_qw<CgABody>(L, tb, nt, first, flip, s);
 }
-hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, bool last, bool flip, hipStream_t s) {
-    return dispatch_qw<CgBBody>(L, tb, nt, last, flip, s);
+hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, bool flip, hipStream_t s) {
+    return dispatch_qw<CgBBody>(L, tb, nt, flip, s);
+}
+hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int np, hipStream_t s) {
+    if (np == 16)
+        hipLaunchKernelGGL((k_finalize<16>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
+    else if (np == 36)
+        hipLaunchKernelGGL((k_finalize<36>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
+    else if (np == 8)
+        hipLaunchKernelGGL((k_finalize<8>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {
     return dispatch_qw<LumpedBody>(L, tb, nt, s);

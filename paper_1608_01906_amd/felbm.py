@@ -29,7 +29,8 @@ ABI_SYMBOLS = ["fel_create", "fel_upload_mesh", "fel_workspace_size", "fel_bind"
 
 class FelOptions(C.Structure):
     _fields_ = [("lattice", C.c_int), ("precision", C.c_int), ("mass_mode", C.c_int), ("cg_iters", C.c_int),
-                ("cg_tol", C.c_double), ("laplacian_mode", C.c_int), ("max_instances", C.c_int)]
+                ("cg_tol", C.c_double), ("laplacian_mode", C.c_int), ("max_instances", C.c_int),
+                ("node_order", C.c_int)]
 
 
 class FelPhys(C.Structure):
@@ -104,9 +105,10 @@ class Context:
     """One felbm context: instances uploaded, bound to a torch workspace/stream."""
 
     def __init__(self, lattice: int, *, precision: str = "fp64", mass_mode: int = 0, cg_iters: int = 0,
-                 cg_tol: float = 0.0, laplacian_mode: int = 0, max_instances: int = 1):
+                 cg_tol: float = 0.0, laplacian_mode: int = 0, max_instances: int = 1, node_order: int = 0):
         self.lib = load_library()
-        opt = FelOptions(lattice, PREC[precision], mass_mode, cg_iters, cg_tol, laplacian_mode, max_instances)
+        opt = FelOptions(lattice, PREC[precision], mass_mode, cg_iters, cg_tol, laplacian_mode, max_instances,
+                         node_order)
         h = _vp()
         st = self.lib.fel_create(C.byref(opt), C.byref(h))
         if st != FEL_OK:
