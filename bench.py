@@ -26,15 +26,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, first_frac: float = 0.0) -> float:
+def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, dev: bool,
+                 first_frac: float = 0.0) -> float:
     """Algorithmic HBM bytes per node row of one launch of a kernel class:
     every operand read or written once (gathers of neighbour values served
-    by cache), pattern = 4-byte column index per slot."""
+    by cache), pattern = 4-byte column index per slot.  s = operator/vector
+    value size, sp = stored population size, dev = deviation storage with
+    two 4-byte node references."""
     NP = 2 * (Q - 1)
     P = 2 * Q
     pat = W * 4
+    ref = 8 if dev else 0
     if cls == "stream":
-        return NP * sp + (2 * sp if sp != 8 and sp != 4 else 0) + pat + NB * W * s + NP * s
+        return NP * sp + ref + pat + NB * W * s + NP * s
     if cls == "cg_init":
         return 3 * NP * s + pat + W * s + s
     if cls == "cg_a":
@@ -44,44 +48,94 @@ def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, 
     if cls == "lumped":
         return 2 * NP * s + s
     if cls == "moments":
-        return Q * sp + (Q - 1) * s + 4 + s
+        return Q * sp + (Q - 1) * s + 4 + s + ref // 2
     if cls == "grad":
         return s + pat + D * W * s + D * s
     if cls == "div":
         return D * s + s + pat + D * W * s + (1 + D) * s
     if cls == "collide":
-        return 2 * P * sp + NP * s + (2 + 2 * D) * s + pat + D * W * s + s + 4 + (D + 1) * s
+        return 2 * P * sp + NP * s + (2 + 2 * D) * s + pat + D * W * s + s + 4 + (D + 1) * s + 2 * ref
     return 0.0
 
 
 def cpu_baseline(workload, target_s: float = 15.0):
+    """The FP64 oracle, as it stands, on the same workload for ~target_s of CPU time."""
     from oracle import oracle as O
     inst = workload.instances[0]
     o = O.Oracle(inst.mesh, workload.lattice, inst.phys)
     o.init(inst.rho0, inst.u0, inst.p0)
     t0 = time.perf_counter()
     o.step(1)
-    t1 = time.perf_counter()
-    per = t1 - t0
+    per = time.perf_counter() - t0
     more = max(1, int(target_s / max(per, 1e-3)) - 1)
     o.step(more)
-    t2 = time.perf_counter()
+    secs = time.perf_counter() - t0
     steps = 1 + more
-    secs = t2 - t0
     N = inst.mesh["xyz"].shape[0]
-    return dict(value=N * 2 * workload.lattice * steps / secs, unit="NPU/s", cores=1, kind="oracle",
-                sample=f"{steps} steps of the same {N}-node workload, plain FP64 C oracle, 1 thread, "
-                       f"{secs:.1f} s")
+    out = dict(value=N * 2 * workload.lattice * steps / secs, unit="NPU/s", cores=1, kind="oracle",
+               sample=f"first {steps} steps of the same {N}-node workload (plain FP64 C oracle, 1 thread, "
+                      f"{secs:.1f} s)")
+    return out, o, steps
+
+
+def run_gpu(w, precision, steps, warmup, prof_steps):
+    import torch
+    from paper_1608_01906_amd import felbm
+    N = w.n_nodes
+    P = 2 * w.lattice
+    ctx = felbm.from_workload(w, precision=precision, device="cuda:0")
+    info = ctx.layout_info()
+    ctx.step(warmup)
+    ctx.sync(allow_notconv=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    ctx.sync(allow_notconv=True)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    # event-timed pass: the same step graph with an event pair around every kernel
+    ctx.profile(True)
+    ctx.step(prof_steps)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    s = 8 if precision == "fp64" else 4
+    sp = {"fp64": 8, "fp32": 4, "fp32_fp16": 2}[precision]
+    D = 2 if w.lattice == 9 else 3
+    NB = 5 if D == 2 else 9
+    kern = {}
+    for name, (cnt, ms) in prof.items():
+        if cnt == 0:
+            continue
+        first = (1.0 / info["cg_iters"]) if name == "cg_a" and info["cg_iters"] else 0.0
+        b = kernel_bytes(name, Q=w.lattice, D=D, W=info["ell_width"], NB=NB, s=s, sp=sp,
+                         dev=precision != "fp64", first_frac=first) * N
+        avg_ms = ms / cnt
+        kern[name] = dict(launches=cnt, avg_us=round(avg_ms * 1e3, 3), total_ms=round(ms, 3),
+                          bytes_per_launch=int(b), gbs=round(b / (avg_ms * 1e-3) / 1e9, 1))
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    dk = kern[dom]
+    step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in kern.values()) / prof_steps
+    res = dict(value=N * P * steps / secs, ms_per_step=secs / steps * 1e3, cg_iters=info["cg_iters"],
+               roofline=dict(bound="hbm", kernel=dom, achieved=dk["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                             bytes_per_launch=dk["bytes_per_launch"], avg_launch_us=dk["avg_us"]),
+               step_algorithmic_gbs=round(step_bytes / (secs / steps) / 1e9, 1),
+               step_frac=round(step_bytes / (secs / steps) / 1e9 / HBM_PEAK_GBS, 4),
+               kernels=kern,
+               event_ms_per_step=round(sum(v["total_ms"] for v in kern.values()) / prof_steps, 4))
+    return res, ctx
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32_fp16"])
-    ap.add_argument("--profile-steps", type=int, default=0, help="steps of the event-timed pass (default: --steps)")
+    ap.add_argument("--steps", type=int, default=5000, help="timed steps (the workload's full length)")
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp32_fp16"],
+                    help="precision of the headline value (the FP64 plain path is measured beside it)")
+    ap.add_argument("--profile-steps", type=int, default=100, help="steps of the event-timed pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -90,81 +144,55 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_1608_01906_amd import felbm
     from paper_1608_01906_amd.inputs import channel2d
+    from tests._parity import compare_fields
 
     w = channel2d()
     inst = w.instances[0]
     N = inst.mesh["xyz"].shape[0]
-    Q = w.lattice
-    P = 2 * Q
-    ctx = felbm.from_workload(w, precision=args.precision, device="cuda:0")
-    info = ctx.layout_info()
-    ctx.step(args.warmup)
-    ctx.sync(allow_notconv=True)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(args.steps)
-    ctx.sync(allow_notconv=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    secs = t1 - t0
-    value = N * P * args.steps / secs
-
-    # event-timed pass (same kernels, one launch at a time) for the roofline
-    psteps = args.profile_steps or args.steps
-    ctx.profile(True)
-    ctx.step(psteps)
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    s = 8 if args.precision == "fp64" else 4
-    sp = {"fp64": 8, "fp32": 4, "fp32_fp16": 2}[args.precision]
-    D = 2
-    W = info["ell_width"]
-    NB = 5
-    kern = {}
-    for name, (cnt, ms) in prof.items():
-        if cnt == 0:
-            continue
-        frac_first = (1.0 / info["cg_iters"]) if name == "cg_a" and info["cg_iters"] else 0.0
-        b = kernel_bytes(name, Q=Q, D=D, W=W, NB=NB, s=s, sp=sp, first_frac=frac_first) * N
-        avg_ms = ms / cnt
-        kern[name] = dict(launches=cnt, avg_us=avg_ms * 1e3, total_ms=ms, bytes_per_launch=b,
-                          gbs=b / (avg_ms * 1e-3) / 1e9)
-    dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    dk = kern[dom]
-    step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in kern.values()) / psteps
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(dk["gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
-                    bytes_per_launch=int(dk["bytes_per_launch"]), avg_launch_us=round(dk["avg_us"], 2))
-    prof_step_ms = sum(v["total_ms"] for v in kern.values()) / psteps
-
+    P = 2 * w.lattice
+    head, ctx_head = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps)
     out = {
         "metric": "node-population updates/s (NPU/s)",
-        "value": value,
+        "value": head["value"],
         "unit": "NPU/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": secs / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp32_fp16": "f32 (f16 storage)"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": "channel2d 1024x256 jittered P1, D2Q9, density ratio 1000, viscosity ratio 50",
+        "config": {"workload": "channel2d: layered two-phase Poiseuille channel, 1024x256 jittered P1 mesh, "
+                               "D2Q9, density ratio 1000, viscosity ratio 50",
                    "nodes": N, "populations": P, "precision": args.precision,
-                   "mass": "consistent, CG x%d" % info["cg_iters"], "dt": inst.phys.dt},
-        "roofline": roofline,
-        "step_hbm_gbs": round(step_bytes / (secs / args.steps) / 1e9, 1),
-        "kernels": {k: {kk: round(vv, 3) if isinstance(vv, float) else vv for kk, vv in v.items()}
-                    for k, v in kern.items()},
-        "profiled_ms_per_step": prof_step_ms,
+                   "mass": f"consistent, CG x{head['cg_iters']}", "dt": inst.phys.dt},
+        "roofline": head["roofline"],
+        "step_algorithmic_gbs": head["step_algorithmic_gbs"],
+        "step_frac": head["step_frac"],
+        "kernels": head["kernels"],
+        "event_ms_per_step": head["event_ms_per_step"],
     }
+    ctx64 = None
+    if not args.no_fp64 and args.precision != "fp64":
+        r64, ctx64 = run_gpu(w, "fp64", args.steps, args.warmup, args.profile_steps)
+        out["fp64_plain"] = {k: r64[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
+                                                 "step_frac", "event_ms_per_step")}
+        out["speedup_vs_fp64_plain"] = head["value"] / r64["value"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        from paper_1608_01906_amd import felbm
+        cb, orc, s_steps = cpu_baseline(w)
+        out["cpu_baseline"] = cb
+        ref = orc.fields()
+        errs = {}
+        for prec in [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"]):
+            c = felbm.from_workload(w, precision=prec, device="cuda:0")
+            c.step(s_steps)
+            c.sync(allow_notconv=True)
+            errs[prec] = {k: float(f"{v:.3e}") for k, v in compare_fields(c.read_fields(0), ref, inst).items()}
+        out["error_vs_oracle"] = dict(steps=s_steps, norm="max |dev - oracle| / max(|oracle|, floor)", **errs)
     print(json.dumps(out), flush=True)
 
 

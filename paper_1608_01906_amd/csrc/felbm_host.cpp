@@ -649,11 +649,12 @@ hipEvent_t get_event(fel_ctx* c) {
 
 template <typename F>
 hipError_t timed(fel_ctx* c, int cls, F&& launch) {
+    (void)hipGetLastError();  // launches report hipGetLastError: clear anything left by earlier calls
     if (!c->profiling) return launch();
     ProfEvent pe{cls, get_event(c), get_event(c)};
-    if (pe.a) (void)hipEventRecord(pe.a, c->stream);
+    if (pe.a && pe.b) g_launch_events = LaunchEvents{pe.a, pe.b};
     hipError_t e = launch();
-    if (pe.b) (void)hipEventRecord(pe.b, c->stream);
+    g_launch_events = LaunchEvents{};
     c->pending.push_back(pe);
     return e;
 }
@@ -702,6 +703,8 @@ fel_status drain_profile(fel_ctx* c) {
         if (pe.a && pe.b && hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
             c->prof_ms[pe.cls] += ms;
             c->prof_count[pe.cls]++;
+        } else {
+            (void)hipGetLastError();
         }
         if (pe.a) c->event_pool.push_back(pe.a);
         if (pe.b) c->event_pool.push_back(pe.b);
@@ -784,6 +787,7 @@ fel_status fel_step(fel_ctx* c, int n_steps) {
     if (!c->bound || !all_initialised(c)) return fail(c, FEL_ESTATE, "step before bind/init_fields");
     if (n_steps == 0) return FEL_OK;
     if (c->profiling || !c->use_graph) {
+        // profiling launches directly: each kernel's events are stamped by its own dispatch
         for (int i = 0; i < n_steps; i++) {
             hipError_t e = enqueue_step(c);
             if (e != hipSuccess) return fail(c, FEL_EDEVICE, "launch failed: %s", hipGetErrorString(e));

@@ -86,6 +86,12 @@ enum KernelClass {
 
 const char* kernel_class_name(int k);
 
+// Events the next launch records around the kernel's own execution (profiling).
+struct LaunchEvents {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
 // Launchers (felbm_kernels.hip).  tile_begin/ntiles select the tile range;
 // every launcher returns the hipError_t of the launch.
 hipError_t launch_stream(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);

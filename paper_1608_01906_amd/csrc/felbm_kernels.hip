@@ -14,7 +14,22 @@
 // bitwise reproducible.
 #include "felbm_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace fel {
+
+thread_local LaunchEvents g_launch_events;
+
+// With a pair of events armed, the launch goes through
+// hipExtLaunchKernelGGL, whose events are stamped by the kernel's own
+// dispatch: the elapsed time is the kernel's execution, without host gaps.
+#define FEL_LAUNCH(K, G, B, SH, S, ...)                                                                    \
+    do {                                                                                                  \
+        if (g_launch_events.a)                                                                            \
+            hipExtLaunchKernelGGL(K, G, B, SH, S, g_launch_events.a, g_launch_events.b, 0, __VA_ARGS__); \
+        else                                                                                              \
+            hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                                              \
+    } while (0)
 
 // ---------------------------------------------------------------------------
 // lattices (standard D2Q9 / D3Q19, cs^2 = 1/3)
@@ -961,6 +976,7 @@ __global__ __launch_bounds__(TILE) void k_sums_dev(DevLayout L, int tile_begin) 
 // run body<Q, W>() for the context's lattice and ELL width
 template <template <int, int> class Body, typename... A>
 static hipError_t dispatch_qw(const DevLayout& L, A... args) {
+    (void)hipGetLastError();  // the launch status is read with hipGetLastError: start clean
     if (L.Q == 9) {
         if (L.W == 7) return Body<9, 7>::run(L, args...);
         if (L.W == 12) return Body<9, 12>::run(L, args...);
@@ -974,11 +990,11 @@ static hipError_t dispatch_qw(const DevLayout& L, A... args) {
 template <int Q, int W> struct StreamBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_stream_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_stream_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else if (L.precision == 1)
-            hipLaunchKernelGGL((k_stream_dev<Q, W, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_stream_dev<Q, W, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else
-            hipLaunchKernelGGL((k_stream_dev<Q, W, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_stream_dev<Q, W, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -986,9 +1002,9 @@ template <int Q, int W> struct CgInitBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_cg_init<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_cg_init<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else
-            hipLaunchKernelGGL((k_cg_init<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_cg_init<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -996,9 +1012,9 @@ template <int Q, int W> struct CgABody {
     static hipError_t run(const DevLayout& L, int tb, int nt, bool first, bool flip, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_cg_a<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)first, (int)flip);
+            FEL_LAUNCH((k_cg_a<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)first, (int)flip);
         else
-            hipLaunchKernelGGL((k_cg_a<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)first, (int)flip);
+            FEL_LAUNCH((k_cg_a<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)first, (int)flip);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -1006,9 +1022,9 @@ template <int Q, int W> struct CgBBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, bool flip, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_cg_b<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)flip);
+            FEL_LAUNCH((k_cg_b<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)flip);
         else
-            hipLaunchKernelGGL((k_cg_b<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)flip);
+            FEL_LAUNCH((k_cg_b<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)flip);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -1016,20 +1032,20 @@ template <int Q, int W> struct LumpedBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_lumped<double, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_lumped<double, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else
-            hipLaunchKernelGGL((k_lumped<float, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_lumped<float, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct MomentsBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_moments_plain<Q>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_moments_plain<Q>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else if (L.precision == 1)
-            hipLaunchKernelGGL((k_moments_dev<Q, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_moments_dev<Q, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else
-            hipLaunchKernelGGL((k_moments_dev<Q, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_moments_dev<Q, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -1037,9 +1053,9 @@ template <int Q, int W> struct GradBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
         constexpr int D = Lat<Q>::D;
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_grad<double, W, D>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_grad<double, W, D>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else
-            hipLaunchKernelGGL((k_grad<float, W, D>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_grad<float, W, D>), dim3(nt), dim3(TILE), 0, s, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -1047,42 +1063,42 @@ template <int Q, int W> struct DivBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
         constexpr int D = Lat<Q>::D;
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_div<double, W, D>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_div<double, W, D>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else
-            hipLaunchKernelGGL((k_div<float, W, D>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_div<float, W, D>), dim3(nt), dim3(TILE), 0, s, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct CollideBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_collide_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_collide_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else if (L.precision == 1)
-            hipLaunchKernelGGL((k_collide_dev<Q, W, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_collide_dev<Q, W, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else
-            hipLaunchKernelGGL((k_collide_dev<Q, W, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_collide_dev<Q, W, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct InitBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_init_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_init_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else if (L.precision == 1)
-            hipLaunchKernelGGL((k_init_dev<Q, W, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_init_dev<Q, W, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else
-            hipLaunchKernelGGL((k_init_dev<Q, W, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_init_dev<Q, W, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct SumsBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
         if (L.precision == 0)
-            hipLaunchKernelGGL((k_sums_plain<Q>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_sums_plain<Q>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else if (L.precision == 1)
-            hipLaunchKernelGGL((k_sums_dev<Q, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_sums_dev<Q, float>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else
-            hipLaunchKernelGGL((k_sums_dev<Q, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
+            FEL_LAUNCH((k_sums_dev<Q, __half>), dim3(nt), dim3(TILE), 0, s, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -1100,12 +1116,13 @@ hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, bool flip, hipStream_
     return dispatch_qw<CgBBody>(L, tb, nt, flip, s);
 }
 hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int np, hipStream_t s) {
+    (void)hipGetLastError();
     if (np == 16)
-        hipLaunchKernelGGL((k_finalize<16>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
+        FEL_LAUNCH((k_finalize<16>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
     else if (np == 36)
-        hipLaunchKernelGGL((k_finalize<36>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
+        FEL_LAUNCH((k_finalize<36>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
     else if (np == 8)
-        hipLaunchKernelGGL((k_finalize<8>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
+        FEL_LAUNCH((k_finalize<8>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

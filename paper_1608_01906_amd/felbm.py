@@ -56,6 +56,10 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(the HIP library has no fallback)")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7);
+    # loading torch first makes the dynamic loader reuse that one runtime for
+    # the library, so device pointers and streams from torch are native to it.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     for name in ABI_SYMBOLS:
         getattr(lib, name)

@@ -159,16 +159,26 @@ def test_batched_instances(felbm, oracle_mod):
 
 
 def test_graph_replay_deterministic(felbm):
-    """Graph replay and per-launch (profiled) stepping give bitwise equal states."""
+    """Graph replay, the profiled graph and direct launches on the default
+    stream (no graph) give bitwise equal states."""
+    import torch
     w = droplet2d(32, radius=8.0)
     a = felbm.from_workload(w)
     b = felbm.from_workload(w)
+    c = felbm.from_workload(w, stream=torch.cuda.default_stream())
     a.step(7)
     b.profile(True)
     b.step(7)
     prof = b.profile_read()
     b.profile(False)
+    c.step(3)
+    c.step(4)
     assert prof["cg_a"][0] == 7 * 30 and prof["stream"][0] == 7
+    np.testing.assert_array_equal(a.get_state(0), b.get_state(0))
+    np.testing.assert_array_equal(a.get_state(0), c.get_state(0))
+    # replay of the same graph keeps producing identical results
+    a.step(5)
+    b.step(5)
     np.testing.assert_array_equal(a.get_state(0), b.get_state(0))
 
 

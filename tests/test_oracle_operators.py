@@ -171,11 +171,12 @@ def test_mass_solve_matches_dense(case):
 
 def test_streaming_stability_at_run_step(oracle_mod):
     """Spectral radius of the one-direction streaming map I - M^-1 A_alpha:
-    <= 1 at dt = 0.25 and > 1 at dt = 1 on a jittered periodic mesh."""
+    <= 1 at the run step and > 1 at dt = 1 on a jittered periodic mesh."""
     mesh = grid_mesh_2d(10, 10, seed=31)
     N = mesh["xyz"].shape[0]
     M, G, K = dense_operators(mesh)
-    for dt, stable in [(0.25, True), (1.0, False)]:
+    from paper_1608_01906_amd.inputs import DT_RUN
+    for dt, stable in [(DT_RUN, True), (1.0, False)]:
         worst = 0.0
         for c in D2Q9[1:]:
             T = np.eye(N) - np.linalg.solve(M, stream_matrix(G, K, c, dt))
