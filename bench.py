@@ -45,6 +45,10 @@ def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, 
         return (3 - first_frac) * NP * s + pat + W * s + s
     if cls == "cg_b":
         return 5 * NP * s + pat + W * s + s
+    if cls == "cheb_first":
+        return 3 * NP * s + pat + W * s + s
+    if cls == "cheb":
+        return 4 * NP * s + pat + W * s + s
     if cls == "lumped":
         return 2 * NP * s + s
     if cls == "moments":
@@ -78,12 +82,12 @@ def cpu_baseline(workload, target_s: float = 15.0):
     return out, o, steps
 
 
-def run_gpu(w, precision, steps, warmup, prof_steps):
+def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0):
     import torch
     from paper_1608_01906_amd import felbm
     N = w.n_nodes
     P = 2 * w.lattice
-    ctx = felbm.from_workload(w, precision=precision, device="cuda:0")
+    ctx = felbm.from_workload(w, precision=precision, device="cuda:0", mass_mode=mass_mode)
     info = ctx.layout_info()
     ctx.step(warmup)
     ctx.sync(allow_notconv=True)
@@ -109,6 +113,11 @@ def run_gpu(w, precision, steps, warmup, prof_steps):
         first = (1.0 / info["cg_iters"]) if name == "cg_a" and info["cg_iters"] else 0.0
         b = kernel_bytes(name, Q=w.lattice, D=D, W=info["ell_width"], NB=NB, s=s, sp=sp,
                          dev=precision != "fp64", first_frac=first) * N
+        if name == "cheb":
+            # one first launch (gathers rhs, writes x0 and x1) per K launches
+            K = info["cg_iters"]
+            kw = dict(Q=w.lattice, D=D, W=info["ell_width"], NB=NB, s=s, sp=sp, dev=precision != "fp64")
+            b = (kernel_bytes("cheb_first", **kw) + (K - 1) * kernel_bytes("cheb", **kw)) / K * N
         avg_ms = ms / cnt
         kern[name] = dict(launches=cnt, avg_us=round(avg_ms * 1e3, 3), total_ms=round(ms, 3),
                           bytes_per_launch=int(b), gbs=round(b / (avg_ms * 1e-3) / 1e9, 1))
@@ -136,6 +145,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100, help="steps of the event-timed pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison run")
+    ap.add_argument("--no-chebyshev", action="store_true",
+                    help="skip the run with the mass matrix solved by Chebyshev iteration")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -181,6 +192,10 @@ def main():
         out["fp64_plain"] = {k: r64[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
                                                  "step_frac", "event_ms_per_step")}
         out["speedup_vs_fp64_plain"] = head["value"] / r64["value"]
+    if not args.no_chebyshev:
+        rch, _ = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, mass_mode=2)
+        out["chebyshev_solve"] = {k: rch[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
+                                                      "step_frac", "event_ms_per_step")}
     if not args.no_cpu_baseline:
         from paper_1608_01906_amd import felbm
         cb, orc, s_steps = cpu_baseline(w)

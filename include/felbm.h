@@ -72,6 +72,10 @@ typedef enum {
 
 #define FEL_MASS_CONSISTENT 0  /* solve with the consistent mass matrix (conjugate gradients) */
 #define FEL_MASS_LUMPED 1      /* lumped-mass approximation (end of Section 2.2.1) */
+#define FEL_MASS_CHEBYSHEV 2   /* consistent mass, Chebyshev semi-iteration preconditioned by the lumped
+                                  mass with the a-priori spectrum bounds [1/(d+2), 1] of m^-1 M: the
+                                  same solution as CG to the same contraction per iteration, no inner
+                                  products (cg_iters iterations; cg_tol unused) */
 
 #define FEL_ORDER_CALLER 0     /* device rows follow the caller's node order */
 #define FEL_ORDER_ZCURVE 1     /* device rows follow a Z-order (Morton) curve of the node positions */
@@ -83,7 +87,8 @@ typedef struct {
     int lattice;          /* FEL_LATTICE_D2Q9 or FEL_LATTICE_D3Q19 */
     int precision;        /* FEL_PREC_* */
     int mass_mode;        /* FEL_MASS_* */
-    int cg_iters;         /* CG iterations per solve; 0 = default (2-D: 30 FP64 / 15 FP32; 3-D: 34 / 17) */
+    int cg_iters;         /* CG (or Chebyshev) iterations per solve; 0 = default (2-D: 30 FP64 / 15 FP32;
+                             3-D: 34 / 17) */
     double cg_tol;        /* after the last iteration, sqrt(r.z / r0.z0) above this flags FEL_ENOTCONV;
                              0 = default (1e-11 FP64, 1e-5 FP32) */
     int laplacian_mode;   /* FEL_LAP_* */

@@ -247,7 +247,7 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
     *out = nullptr;
     if (opt->lattice != 9 && opt->lattice != 19) return FEL_EINVAL;
     if (opt->precision < 0 || opt->precision > 2) return FEL_EINVAL;
-    if (opt->mass_mode != 0 && opt->mass_mode != 1) return FEL_EINVAL;
+    if (opt->mass_mode < 0 || opt->mass_mode > 2) return FEL_EINVAL;
     if (opt->laplacian_mode != 0 && opt->laplacian_mode != 1) return FEL_EINVAL;
     if (opt->max_instances < 1 || opt->max_instances > 65536) return FEL_EINVAL;
     if (opt->cg_iters < 0 || opt->cg_iters > 1000 || opt->cg_tol < 0.0) return FEL_EINVAL;
@@ -665,6 +665,24 @@ hipError_t enqueue_solve(fel_ctx* c, int tb, int nt) {
     hipError_t e;
     if (c->opt.mass_mode == FEL_MASS_LUMPED) {
         return timed(c, KC_LUMPED, [&] { return launch_lumped(L, tb, nt, s); });
+    }
+    if (c->opt.mass_mode == FEL_MASS_CHEBYSHEV) {
+        // spectrum of m^-1 M in [1/(d+2), 1]; iterate count cg_iters
+        const double a = 1.0 / (c->lat.D + 2), b = 1.0;
+        const double theta = 0.5 * (b + a), sigma = (b - a) / (b + a), gamma = 1.0 / theta;
+        const int K = c->cg_iters;
+        const int out0 = (K % 2 == 0) ? 0 : 1;  // x_K must land in buffer 0 (X)
+        if ((e = timed(c, KC_CHEB, [&] { return launch_cheb_first(L, tb, nt, out0, gamma, s); })) != hipSuccess)
+            return e;
+        double omega = 1.0;
+        int cur = 1 - out0;  // buffer holding x_1
+        for (int k = 1; k < K; k++) {
+            omega = (k == 1) ? 1.0 / (1.0 - 0.5 * sigma * sigma) : 1.0 / (1.0 - 0.25 * sigma * sigma * omega);
+            if ((e = timed(c, KC_CHEB, [&] { return launch_cheb(L, tb, nt, cur, omega, gamma, s); })) != hipSuccess)
+                return e;
+            cur = 1 - cur;
+        }
+        return hipSuccess;
     }
     const int ni = c->ninst, np = c->NP;
     auto fin = [&](int op) { return timed(c, KC_FINALIZE, [&] { return launch_finalize(L, 0, ni, op, np, s); }); };

@@ -81,6 +81,7 @@ enum KernelClass {
     KC_INIT,
     KC_SUMS,
     KC_FINALIZE,
+    KC_CHEB,
     KC_COUNT
 };
 
@@ -101,6 +102,11 @@ hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool flip
 // op: 0 CG init, 1 alpha, 2 beta, 3 final residual check, 4 conserved sums; np values per tile
 hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int np, hipStream_t s);
 hipError_t launch_lumped(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+// Chebyshev solve: first launch writes x_0 to buffer out0 and x_1 to the
+// other (0 = X, 1 = Pa); each later launch reads x_k from buffer cur.
+hipError_t launch_cheb_first(const DevLayout& L, int tile_begin, int ntiles, int out0, double gamma, hipStream_t s);
+hipError_t launch_cheb(const DevLayout& L, int tile_begin, int ntiles, int cur, double omega, double gamma,
+                       hipStream_t s);
 hipError_t launch_moments(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_grad(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_div(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);

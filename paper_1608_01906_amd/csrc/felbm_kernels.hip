@@ -71,7 +71,7 @@ template <> struct Lat<19> {
 
 const char* kernel_class_name(int k) {
     static const char* names[KC_COUNT] = {"stream", "cg_init", "cg_a", "cg_b", "lumped", "moments",
-                                          "grad", "div", "collide", "init", "sums", "finalize"};
+                                          "grad", "div", "collide", "init", "sums", "finalize", "cheb"};
     return (k >= 0 && k < KC_COUNT) ? names[k] : "?";
 }
 
@@ -130,28 +130,28 @@ struct TileReducer {
 // What a finalize launch does with the instance totals.
 enum FinOp { FIN_CG_INIT = 0, FIN_CG_A, FIN_CG_B, FIN_CG_LAST, FIN_SUMS };
 
-// One block per instance: sums the instance's tile partials in a fixed
-// order and derives the CG scalars (or stores the conserved sums).
-constexpr int FIN_THREADS = 1024;
+// One block per (instance, value j): sums the instance's tile partials of
+// value j in a fixed order (strided per thread, then wavefront shuffles and
+// the waves in order) and derives the CG scalar (or stores the conserved sum).
+constexpr int FIN_THREADS = 256;
 
 template <int NP>
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(DevLayout L, int inst_begin, int op) {
-    __shared__ double fin[FIN_THREADS];
+    __shared__ double fin[FIN_THREADS / 64];
     const int inst = inst_begin + blockIdx.x;
+    const int j = blockIdx.y;
     const int tb = L.params[inst].tile_begin, nt = L.params[inst].tile_count;
-    constexpr int G = FIN_THREADS / NP;
-    const int j = threadIdx.x % NP, g = threadIdx.x / NP;
+    const double* src = L.partial + (int64_t)tb * NP + j;
     double s = 0.0;
-    if (g < G) {
-        const double* src = L.partial + (int64_t)tb * NP + j;
-#pragma unroll 16
-        for (int t = g; t < nt; t += G) s += src[(int64_t)t * NP];
-    }
-    fin[threadIdx.x] = s;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < nt; t += FIN_THREADS) s += src[(int64_t)t * NP];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) fin[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x >= NP) return;
+    if (threadIdx.x != 0) return;
     double tot = 0.0;
-    for (int gg = 0; gg < G; gg++) tot += fin[gg * NP + threadIdx.x];
+#pragma unroll
+    for (int w = 0; w < FIN_THREADS / 64; w++) tot += fin[w];
     const int i = inst * NP + j;
     switch (op) {
     case FIN_CG_INIT:
@@ -354,6 +354,80 @@ __global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int 
         red.add(j, (double)r * (double)r * (double)mrow);
     }
     red.finish(L, tile);
+}
+
+// Chebyshev semi-iteration on M Delta = rhs, preconditioned by the lumped
+// mass, with the a-priori spectrum bounds of m^-1 M ([1/(d+2), 1] for P1
+// simplices, element by element):
+//   x_0 = rhs / m,   x_1 = x_0 + gamma z_0,
+//   x_{k+1} = omega_{k+1} (gamma z_k + x_k - x_{k-1}) + x_{k-1},
+//   z_k = m^-1 (rhs - M x_k).
+// No inner products, so no reductions; sum m x is conserved at every iterate
+// (sum m z_k = 0).  The two iterates live in buf 0 = X and buf 1 = Pa; a
+// launch reads x_k (gathered) and x_{k-1} (own row) and overwrites x_{k-1}.
+template <typename T>
+__device__ __forceinline__ T* cheb_buf(const DevLayout& L, int b) {
+    return reinterpret_cast<T*>(b ? L.Pa : L.X);
+}
+
+template <typename T, int W, int NP>
+__global__ __launch_bounds__(TILE) void k_cheb_first(DevLayout L, int tile_begin, int out0, T gamma) {
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    const int64_t R = L.R;
+    const int row = tile * TILE + threadIdx.x;
+    const T* rhs = reinterpret_cast<const T*>(L.Pb);
+    const T* minv = reinterpret_cast<const T*>(L.minv);
+    T* x0 = cheb_buf<T>(L, out0);
+    T* x1 = cheb_buf<T>(L, 1 - out0);
+    int c[W];
+    T mv[W], mi[W];
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+        c[k] = L.col[k * R + row];
+        mv[k] = ld<T>(L.Mval, k * R + row);
+        mi[k] = gat(minv, c[k]);
+    }
+    const T mrow = minv[row];
+#pragma unroll 2
+    for (int j = 0; j < NP; j++) {
+        const T* b = rhs + (int64_t)j * R;
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < W; k++) acc += mv[k] * (gat(b, c[k]) * mi[k]);
+        const T bj = gat(b, row);
+        const T xa = bj * mrow;
+        x0[(int64_t)j * R + row] = xa;
+        x1[(int64_t)j * R + row] = xa + gamma * ((bj - acc) * mrow);
+    }
+}
+
+template <typename T, int W, int NP>
+__global__ __launch_bounds__(TILE) void k_cheb(DevLayout L, int tile_begin, int cur, T omega, T gamma) {
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    const int64_t R = L.R;
+    const int row = tile * TILE + threadIdx.x;
+    const T* rhs = reinterpret_cast<const T*>(L.Pb);
+    const T* xk = cheb_buf<T>(L, cur);
+    T* xp = cheb_buf<T>(L, 1 - cur);
+    int c[W];
+    T mv[W];
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+        c[k] = L.col[k * R + row];
+        mv[k] = ld<T>(L.Mval, k * R + row);
+    }
+    const T mrow = ld<T>(L.minv, row);
+#pragma unroll 2
+    for (int j = 0; j < NP; j++) {
+        const T* x = xk + (int64_t)j * R;
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < W; k++) acc += mv[k] * gat(x, c[k]);
+        const int64_t i = (int64_t)j * R + row;
+        const T z = (rhs[i] - acc) * mrow;
+        const T xprev = xp[i];
+        xp[i] = omega * (gamma * z + gat(x, row) - xprev) + xprev;
+    }
 }
 
 // lumped-mass approximation: Delta = rhs / m
@@ -1118,15 +1192,42 @@ hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, bool flip, hipStream_
 hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int np, hipStream_t s) {
     (void)hipGetLastError();
     if (np == 16)
-        FEL_LAUNCH((k_finalize<16>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
+        FEL_LAUNCH((k_finalize<16>), dim3(ninst, 16), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
     else if (np == 36)
-        FEL_LAUNCH((k_finalize<36>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
+        FEL_LAUNCH((k_finalize<36>), dim3(ninst, 36), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
     else if (np == 8)
-        FEL_LAUNCH((k_finalize<8>), dim3(ninst), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
+        FEL_LAUNCH((k_finalize<8>), dim3(ninst, 8), dim3(FIN_THREADS), 0, s, L, inst_begin, op);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
+template <int Q, int W> struct ChebFirstBody {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int out0, double gamma, hipStream_t s) {
+        constexpr int NP = 2 * (Q - 1);
+        if (L.precision == 0)
+            FEL_LAUNCH((k_cheb_first<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, out0, gamma);
+        else
+            FEL_LAUNCH((k_cheb_first<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, out0, (float)gamma);
+        FEL_CHECK_LAUNCH();
+    }
+};
+template <int Q, int W> struct ChebBody {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma, hipStream_t s) {
+        constexpr int NP = 2 * (Q - 1);
+        if (L.precision == 0)
+            FEL_LAUNCH((k_cheb<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, cur, omega, gamma);
+        else
+            FEL_LAUNCH((k_cheb<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, cur, (float)omega, (float)gamma);
+        FEL_CHECK_LAUNCH();
+    }
+};
+hipError_t launch_cheb_first(const DevLayout& L, int tb, int nt, int out0, double gamma, hipStream_t s) {
+    return dispatch_qw<ChebFirstBody>(L, tb, nt, out0, gamma, s);
+}
+hipError_t launch_cheb(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma, hipStream_t s) {
+    return dispatch_qw<ChebBody>(L, tb, nt, cur, omega, gamma, s);
+}
+
 hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {
     return dispatch_qw<LumpedBody>(L, tb, nt, s);
 }

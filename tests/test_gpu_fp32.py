@@ -141,3 +141,15 @@ def test_fp32_full_size_channel_prefix(felbm, oracle_mod):
     e = _errs(ctx, o, inst, label="fp32 channel full 2")
     for k in ("rho", "u", "C"):
         assert e[k] < TOL32, (k, e[k])
+
+
+def test_fp32_chebyshev_channel(felbm, oracle_mod):
+    w = channel2d(nx=20, ny=37)
+    inst = w.instances[0]
+    ctx = felbm.from_workload(w, precision="fp32", mass_mode=2)
+    ctx.step(30)
+    ctx.sync()
+    o = _oracle(oracle_mod, inst, 9, 30)
+    e = _errs(ctx, o, inst, label="fp32 chebyshev channel 30")
+    for k in ("rho", "u", "C"):
+        assert e[k] < TOL32, (k, e[k])
