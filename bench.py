@@ -25,6 +25,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+DESCRIPTIONS = {
+    "channel2d": "channel2d: layered two-phase Poiseuille channel, 1024x256 jittered P1 mesh, D2Q9, "
+                 "density ratio 1000, viscosity ratio 50",
+    "droplet2d": "droplet2d: static drop, 64x64 periodic jittered P1 mesh, D2Q9, density ratio 10",
+    "rt2d": "rt2d: Rayleigh-Taylor, 1024x4096 jittered P1 mesh between walls, D2Q9, Atwood 0.5",
+    "droplet3d": "droplet3d: static drop, 128^3 periodic jittered Kuhn-tet mesh, D3Q19, density ratio 100",
+    "ensemble2d": "ensemble2d: 64 independent periodic drops, sides 32..512, density ratios 1..1000, D2Q9",
+}
+
 
 def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, dev: bool,
                  first_frac: float = 0.0) -> float:
@@ -82,7 +91,24 @@ def cpu_baseline(workload, target_s: float = 15.0):
     return out, o, steps
 
 
-def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0):
+def measured_traffic(workload: str, precision: str, mass_mode: int, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by their copy-kernel
+    calibration), or None when no summary covers this configuration or the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic_{precision}_mass{mass_mode}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1608_01906_amd", "csrc", "felbm_kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["kernel_source_sha256_16"]:
+        return None
+    k = rec["kernels"].get(kernel)
+    return k["traffic_bytes"] if k else None
+
+
+def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="channel2d"):
     import torch
     from paper_1608_01906_amd import felbm
     N = w.n_nodes
@@ -94,13 +120,20 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.step(steps)
-    ctx.sync(allow_notconv=True)
+    status = "ok"
+    try:
+        ctx.sync(allow_notconv=True)
+    except felbm.FelError as e:  # the state went non-finite; the timing still stands
+        status = str(e)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     # event-timed pass: the same step graph with an event pair around every kernel
     ctx.profile(True)
     ctx.step(prof_steps)
-    prof = ctx.profile_read()
+    try:
+        prof = ctx.profile_read()
+    except felbm.FelError:
+        prof = ctx.profile_read()
     ctx.profile(False)
     s = 8 if precision == "fp64" else 4
     sp = {"fp64": 8, "fp32": 4, "fp32_fp16": 2}[precision]
@@ -125,8 +158,10 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0):
     dk = kern[dom]
     step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in kern.values()) / prof_steps
     res = dict(value=N * P * steps / secs, ms_per_step=secs / steps * 1e3, cg_iters=info["cg_iters"],
+               status=status,
                roofline=dict(bound="hbm", kernel=dom, achieved=dk["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                             frac=round(dk["gbs"] / HBM_PEAK_GBS, 4),
+                             traffic=measured_traffic(workload, precision, mass_mode, dom),
                              bytes_per_launch=dk["bytes_per_launch"], avg_launch_us=dk["avg_us"]),
                step_algorithmic_gbs=round(step_bytes / (secs / steps) / 1e9, 1),
                step_frac=round(step_bytes / (secs / steps) / 1e9 / HBM_PEAK_GBS, 4),
@@ -145,6 +180,10 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100, help="steps of the event-timed pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison run")
+    ap.add_argument("--workload", default="channel2d", choices=sorted(DESCRIPTIONS),
+                    help="workload (default: the 1024 x 256 layered channel)")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="first copy this many MiB device-to-device (HBM counter calibration)")
     ap.add_argument("--no-chebyshev", action="store_true",
                     help="skip the run with the mass matrix solved by Chebyshev iteration")
     args = ap.parse_args()
@@ -155,14 +194,23 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    from paper_1608_01906_amd.inputs import channel2d
+    from paper_1608_01906_amd.inputs import WORKLOADS
     from tests._parity import compare_fields
 
-    w = channel2d()
+    if args.copy_probe:
+        # a plain device copy of known size, for calibrating the HBM counters
+        import torch
+        nb = int(args.copy_probe * 2 ** 20)
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    w = WORKLOADS[args.workload]()
     inst = w.instances[0]
-    N = inst.mesh["xyz"].shape[0]
+    N = w.n_nodes
     P = 2 * w.lattice
-    head, ctx_head = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps)
+    head, ctx_head = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, workload=args.workload)
     out = {
         "metric": "node-population updates/s (NPU/s)",
         "value": head["value"],
@@ -176,8 +224,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp32_fp16": "f32 (f16 storage)"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": "channel2d: layered two-phase Poiseuille channel, 1024x256 jittered P1 mesh, "
-                               "D2Q9, density ratio 1000, viscosity ratio 50",
+        "config": {"workload": DESCRIPTIONS.get(args.workload, w.name), "instances": len(w.instances),
                    "nodes": N, "populations": P, "precision": args.precision,
                    "mass": f"consistent, CG x{head['cg_iters']}", "dt": inst.phys.dt},
         "roofline": head["roofline"],
@@ -185,15 +232,17 @@ def main():
         "step_frac": head["step_frac"],
         "kernels": head["kernels"],
         "event_ms_per_step": head["event_ms_per_step"],
+        "status": head["status"],
     }
     ctx64 = None
     if not args.no_fp64 and args.precision != "fp64":
-        r64, ctx64 = run_gpu(w, "fp64", args.steps, args.warmup, args.profile_steps)
+        r64, ctx64 = run_gpu(w, "fp64", args.steps, args.warmup, args.profile_steps, workload=args.workload)
         out["fp64_plain"] = {k: r64[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
                                                  "step_frac", "event_ms_per_step")}
         out["speedup_vs_fp64_plain"] = head["value"] / r64["value"]
     if not args.no_chebyshev:
-        rch, _ = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, mass_mode=2)
+        rch, _ = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, mass_mode=2,
+                         workload=args.workload)
         out["chebyshev_solve"] = {k: rch[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
                                                       "step_frac", "event_ms_per_step")}
     if not args.no_cpu_baseline:

@@ -121,7 +121,7 @@ def droplet2d(n=64, *, jitter=0.2, seed=1608, radius=None, rho_l=1.0, rho_v=0.1,
 
 
 def droplet3d(n=128, *, jitter=0.2, seed=1611, radius=None, rho_l=1.0, rho_v=0.01, sigma=0.005,
-              xi=4.0, tau=0.05, steps=500) -> Workload:
+              xi=8.0, tau=0.05, steps=500) -> Workload:
     mesh = grid_mesh_3d(n, n, n, jitter=jitter, seed=seed)
     inst = droplet_instance(mesh, radius=radius if radius is not None else n / 4.0,
                             rho_l=rho_l, rho_v=rho_v, sigma=sigma, xi=xi, tau_l=tau, tau_v=tau,
@@ -199,7 +199,7 @@ def rt2d(nx=1024, ny=4096, *, jitter=0.2, seed=1610, rho_heavy=1.0, rho_light=1.
                     "D2Q9 Rayleigh-Taylor, heavy over light, walls top and bottom")
 
 
-def ensemble2d(count=64, *, side_lo=32, side_hi=512, seed=16085, jitter=0.2, sigma=0.01, xi=4.0,
+def ensemble2d(count=64, *, side_lo=32, side_hi=512, seed=16085, jitter=0.2, sigma=0.01, xi=None,
                tau=0.05, steps=1000, ratio_hi=1000.0, ratio_min=1.05) -> Workload:
     """Independent periodic droplets with sides ~ U{lo..hi}, density ratio log-uniform.
 
@@ -219,9 +219,12 @@ def ensemble2d(count=64, *, side_lo=32, side_hi=512, seed=16085, jitter=0.2, sig
     insts = []
     for i, (s, r) in enumerate(zip(sides, ratios)):
         mesh = grid_mesh_2d(int(s), int(s), jitter=jitter, seed=seed * 1000 + i)
-        inst = droplet_instance(mesh, radius=0.25 * s, rho_l=1.0, rho_v=1.0 / r, sigma=sigma, xi=xi,
+        # sharper density ratios need wider interfaces to stay positive in the
+        # light phase; never wider than half the radius
+        w_i = xi if xi is not None else min(4.0 if r <= 10 else (8.0 if r <= 100 else 12.0), 0.125 * s)
+        inst = droplet_instance(mesh, radius=0.25 * s, rho_l=1.0, rho_v=1.0 / r, sigma=sigma, xi=w_i,
                                 tau_l=tau, tau_v=tau, center=np.array([s / 2.0, s / 2.0]))
-        inst.meta.update(side=int(s), ratio=float(r))
+        inst.meta.update(side=int(s), ratio=float(r), xi=w_i)
         insts.append(inst)
     return Workload(f"ensemble2d_{count}", 9, insts, steps,
                     "independent D2Q9 droplets of uneven size advanced together")
