@@ -166,6 +166,7 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="chan
                step_algorithmic_gbs=round(step_bytes / (secs / steps) / 1e9, 1),
                step_frac=round(step_bytes / (secs / steps) / 1e9 / HBM_PEAK_GBS, 4),
                kernels=kern,
+               solver_batch={k: v for k, v in ctx.tuning().items() if k in kern},
                event_ms_per_step=round(sum(v["total_ms"] for v in kern.values()) / prof_steps, 4))
     return res, ctx
 
@@ -231,6 +232,7 @@ def main():
         "step_algorithmic_gbs": head["step_algorithmic_gbs"],
         "step_frac": head["step_frac"],
         "kernels": head["kernels"],
+        "solver_batch": head["solver_batch"],
         "event_ms_per_step": head["event_ms_per_step"],
         "status": head["status"],
     }
@@ -244,7 +246,7 @@ def main():
         rch, _ = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, mass_mode=2,
                          workload=args.workload)
         out["chebyshev_solve"] = {k: rch[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
-                                                      "step_frac", "event_ms_per_step")}
+                                                      "step_frac", "event_ms_per_step", "solver_batch")}
     if not args.no_cpu_baseline:
         from paper_1608_01906_amd import felbm
         cb, orc, s_steps = cpu_baseline(w)

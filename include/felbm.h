@@ -97,6 +97,10 @@ typedef struct {
                              already coalesced (each neighbour slot of 64 consecutive rows is one
                              contiguous run); unstructured meshes in arbitrary order need the curve.
                              Fields always cross the ABI in the caller's order. */
+    int solver_batch;     /* populations whose neighbour loads a mass-solve kernel issues ahead of
+                             use (its software-pipeline depth): 1, 2 or 4 for every solver kernel, or
+                             0 = chosen per kernel by timing the three on the bound layout before the
+                             first step (results are bit-identical whichever is used) */
 } fel_options;
 
 /* Physical parameters of one instance (Section 2.1).  rho_l is the heavy
@@ -193,6 +197,12 @@ FEL_API fel_status fel_profile_read(fel_ctx* ctx, int max_classes, int* n_classe
 /* Sizes of the device layout (for traffic accounting): total padded rows,
  * ELL width, number of stored populations and CG iterations per step. */
 FEL_API fel_status fel_layout_info(fel_ctx* ctx, int64_t* rows, int* ell_width, int* pops, int* cg_iters);
+
+/* Population batch in use for each kernel class k < max_classes (same
+ * classes and order as fel_profile_read; 1 for the kernels without a
+ * tunable batch).  With solver_batch = 0 the solver entries are final after
+ * the first fel_step; before it they read 0. */
+FEL_API fel_status fel_tuning(fel_ctx* ctx, int max_classes, int* n_classes, int* batch);
 
 FEL_API fel_status fel_destroy(fel_ctx* ctx);
 FEL_API const char* fel_last_error(const fel_ctx* ctx);

@@ -16,7 +16,6 @@ using namespace fel;
 
 namespace {
 
-constexpr double CS2 = 1.0 / 3.0;
 
 struct LatticeInfo {
     int Q, D, NB;
@@ -106,6 +105,8 @@ struct fel_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool use_graph = true;
+    // population batch of each kernel class (see run_rows); 0 = not yet tuned
+    int batch[KC_COUNT] = {};
     // profiling
     bool profiling = false;
     std::vector<ProfEvent> pending;
@@ -252,6 +253,8 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
     if (opt->max_instances < 1 || opt->max_instances > 65536) return FEL_EINVAL;
     if (opt->cg_iters < 0 || opt->cg_iters > 1000 || opt->cg_tol < 0.0) return FEL_EINVAL;
     if (opt->node_order != FEL_ORDER_CALLER && opt->node_order != FEL_ORDER_ZCURVE) return FEL_EINVAL;
+    const int nb = opt->solver_batch;
+    if (nb != 0 && nb != 1 && nb != 2 && nb != 4) return FEL_EINVAL;
     fel_ctx* c = new (std::nothrow) fel_ctx();
     if (!c) return FEL_ENOMEM;
     c->opt = *opt;
@@ -263,6 +266,8 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
     c->cg_tol = opt->cg_tol > 0.0 ? opt->cg_tol : (fp64 ? 1e-11 : 1e-5);
     c->NP = 2 * (opt->lattice - 1);
     c->NB = c->lat.NB;
+    for (int k = 0; k < KC_COUNT; k++) c->batch[k] = 1;
+    for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) c->batch[k] = nb;
     *out = c;
     return FEL_OK;
 }
@@ -672,13 +677,13 @@ hipError_t enqueue_solve(fel_ctx* c, int tb, int nt) {
         const double theta = 0.5 * (b + a), sigma = (b - a) / (b + a), gamma = 1.0 / theta;
         const int K = c->cg_iters;
         const int out0 = (K % 2 == 0) ? 0 : 1;  // x_K must land in buffer 0 (X)
-        if ((e = timed(c, KC_CHEB, [&] { return launch_cheb_first(L, tb, nt, out0, gamma, s); })) != hipSuccess)
+        if ((e = timed(c, KC_CHEB, [&] { return launch_cheb_first(L, tb, nt, out0, gamma, c->batch[KC_CHEB], s); })) != hipSuccess)
             return e;
         double omega = 1.0;
         int cur = 1 - out0;  // buffer holding x_1
         for (int k = 1; k < K; k++) {
             omega = (k == 1) ? 1.0 / (1.0 - 0.5 * sigma * sigma) : 1.0 / (1.0 - 0.25 * sigma * sigma * omega);
-            if ((e = timed(c, KC_CHEB, [&] { return launch_cheb(L, tb, nt, cur, omega, gamma, s); })) != hipSuccess)
+            if ((e = timed(c, KC_CHEB, [&] { return launch_cheb(L, tb, nt, cur, omega, gamma, c->batch[KC_CHEB], s); })) != hipSuccess)
                 return e;
             cur = 1 - cur;
         }
@@ -686,17 +691,73 @@ hipError_t enqueue_solve(fel_ctx* c, int tb, int nt) {
     }
     const int ni = c->ninst, np = c->NP;
     auto fin = [&](int op) { return timed(c, KC_FINALIZE, [&] { return launch_finalize(L, 0, ni, op, np, s); }); };
-    if ((e = timed(c, KC_CG_INIT, [&] { return launch_cg_init(L, tb, nt, s); })) != hipSuccess) return e;
+    if ((e = timed(c, KC_CG_INIT, [&] { return launch_cg_init(L, tb, nt, c->batch[KC_CG_INIT], s); })) != hipSuccess) return e;
     if ((e = fin(0)) != hipSuccess) return e;
     for (int it = 0; it < c->cg_iters; it++) {
         const bool flip = (it & 1) != 0;
-        if ((e = timed(c, KC_CG_A, [&] { return launch_cg_a(L, tb, nt, it == 0, flip, s); })) != hipSuccess)
+        if ((e = timed(c, KC_CG_A, [&] { return launch_cg_a(L, tb, nt, it == 0, flip, c->batch[KC_CG_A], s); })) != hipSuccess)
             return e;
         if ((e = fin(1)) != hipSuccess) return e;
-        if ((e = timed(c, KC_CG_B, [&] { return launch_cg_b(L, tb, nt, flip, s); })) != hipSuccess) return e;
+        if ((e = timed(c, KC_CG_B, [&] { return launch_cg_b(L, tb, nt, flip, c->batch[KC_CG_B], s); })) != hipSuccess) return e;
         if ((e = fin(it == c->cg_iters - 1 ? 3 : 2)) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Chooses the population batch of each solver kernel still at 0 (how many
+// populations' loads its pipeline issues ahead) by timing the candidates
+// 1, 2 and 4 on the bound layout.  The launches only touch the
+// solve's scratch vectors (X, Rv, Pa, Pb, tile partials), which the next
+// step's streaming and first solver launch rewrite before reading.
+fel_status tune_batches(fel_ctx* c) {
+    const DevLayout& L = c->L;
+    hipStream_t s = c->stream;
+    const int nt = c->ntiles;
+    const double gamma = 2.0 / (1.0 + 1.0 / (c->lat.D + 2));
+    hipEvent_t a = get_event(c), b = get_event(c);
+    if (!a || !b) return fail(c, FEL_EDEVICE, "event creation failed");
+    auto run = [&](int cls, int t) -> hipError_t {
+        switch (cls) {
+            case KC_CG_INIT: return launch_cg_init(L, 0, nt, t, s);
+            case KC_CG_A: return launch_cg_a(L, 0, nt, false, false, t, s);
+            case KC_CG_B: return launch_cg_b(L, 0, nt, false, t, s);
+            default: return launch_cheb(L, 0, nt, 1, 1.0, gamma, t, s);
+        }
+    };
+    // kernels the mass mode never launches keep batch 1
+    const int mode = c->opt.mass_mode;
+    for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) {
+        const bool used = cls == KC_CHEB ? mode == FEL_MASS_CHEBYSHEV : mode == FEL_MASS_CONSISTENT;
+        if (!used && c->batch[cls] == 0) c->batch[cls] = 1;
+    }
+    constexpr int kWarm = 2, kReps = 8;
+    fel_status st = FEL_OK;
+    for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) {
+        if (c->batch[cls] != 0) continue;
+        int best = 1;
+        float best_ms = 0.0f;
+        for (int t : {1, 2, 4}) {
+            (void)hipGetLastError();
+            hipError_t e = hipSuccess;
+            for (int r = 0; r < kWarm && e == hipSuccess; r++) e = run(cls, t);
+            if (e == hipSuccess) e = hipEventRecord(a, s);
+            for (int r = 0; r < kReps && e == hipSuccess; r++) e = run(cls, t);
+            if (e == hipSuccess) e = hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) {
+                st = fail(c, FEL_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e));
+                break;
+            }
+            if (t == 1 || ms < best_ms) best = t, best_ms = ms;
+        }
+        if (st != FEL_OK) break;
+        c->batch[cls] = best;
+    }
+    c->event_pool.push_back(a);
+    c->event_pool.push_back(b);
+    return st;
 }
 
 hipError_t enqueue_step(fel_ctx* c) {
@@ -804,6 +865,10 @@ fel_status fel_step(fel_ctx* c, int n_steps) {
     if (!c || n_steps < 0) return FEL_EINVAL;
     if (!c->bound || !all_initialised(c)) return fail(c, FEL_ESTATE, "step before bind/init_fields");
     if (n_steps == 0) return FEL_OK;
+    if (!c->batch[KC_CG_INIT] || !c->batch[KC_CG_A] || !c->batch[KC_CG_B] || !c->batch[KC_CHEB]) {
+        fel_status st = tune_batches(c);
+        if (st != FEL_OK) return st;
+    }
     if (c->profiling || !c->use_graph) {
         // profiling launches directly: each kernel's events are stamped by its own dispatch
         for (int i = 0; i < n_steps; i++) {
@@ -1077,6 +1142,14 @@ fel_status fel_layout_info(fel_ctx* c, int64_t* rows, int* ell_width, int* pops,
     if (ell_width) *ell_width = c->W;
     if (pops) *pops = 2 * c->opt.lattice;
     if (cg_iters) *cg_iters = c->opt.mass_mode == FEL_MASS_LUMPED ? 0 : c->cg_iters;
+    return FEL_OK;
+}
+
+fel_status fel_tuning(fel_ctx* c, int max_classes, int* n_classes, int* batch) {
+    if (!c || !n_classes) return FEL_EINVAL;
+    *n_classes = KC_COUNT;
+    for (int k = 0; k < KC_COUNT && k < max_classes; k++)
+        if (batch) batch[k] = c->batch[k];
     return FEL_OK;
 }
 

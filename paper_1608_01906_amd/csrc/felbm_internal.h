@@ -96,16 +96,19 @@ extern thread_local LaunchEvents g_launch_events;
 // Launchers (felbm_kernels.hip).  tile_begin/ntiles select the tile range;
 // every launcher returns the hipError_t of the launch.
 hipError_t launch_stream(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
-hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
-hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, bool flip, hipStream_t s);
-hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool flip, hipStream_t s);
+// the solver launchers take the population batch (1, 2 or 4) of their pipeline
+hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, int batch, hipStream_t s);
+hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, bool flip, int batch,
+                       hipStream_t s);
+hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool flip, int batch, hipStream_t s);
 // op: 0 CG init, 1 alpha, 2 beta, 3 final residual check, 4 conserved sums; np values per tile
 hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int np, hipStream_t s);
 hipError_t launch_lumped(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 // Chebyshev solve: first launch writes x_0 to buffer out0 and x_1 to the
 // other (0 = X, 1 = Pa); each later launch reads x_k from buffer cur.
-hipError_t launch_cheb_first(const DevLayout& L, int tile_begin, int ntiles, int out0, double gamma, hipStream_t s);
-hipError_t launch_cheb(const DevLayout& L, int tile_begin, int ntiles, int cur, double omega, double gamma,
+hipError_t launch_cheb_first(const DevLayout& L, int tile_begin, int ntiles, int out0, double gamma, int batch,
+                             hipStream_t s);
+hipError_t launch_cheb(const DevLayout& L, int tile_begin, int ntiles, int cur, double omega, double gamma, int batch,
                        hipStream_t s);
 hipError_t launch_moments(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_grad(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);

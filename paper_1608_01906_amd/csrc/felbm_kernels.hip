@@ -93,6 +93,34 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Sum over the wavefront of N values per lane (N a power of two <= 64) in
+// log2(N) + log2(64 / N) exchange steps instead of N * 6: at each of the
+// first log2(N) steps a lane pair splits its values in halves, each lane
+// keeps one half and adds the partner's copy of it; plain xor steps finish.
+// Afterwards v[0] of lane l holds the total of value l / (64 / N).  Every
+// step is a commutative pairwise add, so all lanes of a group agree bitwise.
+template <int N, int M>
+struct Butterfly {
+    static __device__ __forceinline__ void run(double* v, int lane) {
+        constexpr int H = N / 2;
+        const bool up = (lane & M) != 0;
+#pragma unroll
+        for (int i = 0; i < H; i++) {
+            const double send = up ? v[i] : v[i + H];
+            const double keep = up ? v[i + H] : v[i];
+            v[i] = keep + __shfl_xor(send, M, 64);
+        }
+        Butterfly<H, M / 2>::run(v, lane);
+    }
+};
+template <int M>
+struct Butterfly<1, M> {
+    static __device__ __forceinline__ void run(double* v, int) {
+#pragma unroll
+        for (int m = M; m >= 1; m >>= 1) v[0] += __shfl_xor(v[0], m, 64);
+    }
+};
+
 template <typename T> __device__ __forceinline__ T ld(const void* p, int64_t i) {
     return reinterpret_cast<const T*>(p)[i];
 }
@@ -115,6 +143,14 @@ struct TileReducer {
     __device__ __forceinline__ void add(int j, double v) {
         v = wave_sum(v);
         if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6][j] = v;
+    }
+    // values j0 .. j0 + G - 1 at once (G a power of two)
+    template <int G>
+    __device__ __forceinline__ void add_group(int j0, double (&v)[G]) {
+        const int lane = threadIdx.x & 63;
+        Butterfly<G, 32>::run(v, lane);
+        constexpr int S = 64 / G;
+        if ((lane & (S - 1)) == 0) lds[threadIdx.x >> 6][j0 + lane / S] = v[0];
     }
     __device__ __forceinline__ void finish(const DevLayout& L, int tile) {
         __syncthreads();
@@ -236,123 +272,221 @@ __global__ __launch_bounds__(TILE) void k_stream_plain(DevLayout L, int tile_beg
 // conjugate gradients on M (batched over populations and instances),
 // lumped preconditioner z = r / m, start x0 = rhs / m.
 
-template <typename T, int W, int NP>
-__global__ __launch_bounds__(TILE) void k_cg_init(DevLayout L, int tile_begin) {
-    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
-    const int inst = L.tile_inst[tile];
-    const int64_t R = L.R;
-    const int row = tile * TILE + threadIdx.x;
-    const T* rhs = reinterpret_cast<const T*>(L.Pb);
-    const T* minv = reinterpret_cast<const T*>(L.minv);
-    int c[W];
-    T mv[W], mi[W];
+// Thread layout of the solver kernels: one thread per row, a block covers
+// one tile of TILE rows, so every wavefront load is 64 consecutive rows of
+// one population.  Each kernel walks the NP populations of its row as a
+// two-stage software pipeline (run_rows): the loads of the next batch of CH
+// populations (neighbour gathers and own-row values) are issued before the
+// current batch is used, so a wave has up to 2 CH populations' loads in
+// flight.  CH (1, 2 or 4) is chosen per kernel by the autotuner.  A batch
+// only writes its own populations' rows and only reads populations or
+// buffers that the launch does not write, so the early loads are safe.
+// The FP64 dot products are reduced RG populations at a time.
+constexpr int RG = 4;
+
+template <int NP, int CH, class Body>
+__device__ __forceinline__ void run_rows(Body& body, TileReducer<NP>* red) {
+    static_assert(NP % CH == 0 && NP % RG == 0, "population batches must tile NP");
+    typename Body::Regs buf[2][CH];
 #pragma unroll
-    for (int k = 0; k < W; k++) {
-        c[k] = L.col[k * R + row];
-        mv[k] = ld<T>(L.Mval, k * R + row);
-        mi[k] = gat(minv, c[k]);
+    for (int u = 0; u < CH; u++) body.load(u, buf[0][u]);
+    double dots[RG];
+#pragma unroll
+    for (int j0 = 0; j0 < NP; j0 += CH) {
+        const int cur = (j0 / CH) & 1;
+        if (j0 + CH < NP) {
+#pragma unroll
+            for (int u = 0; u < CH; u++) body.load(j0 + CH + u, buf[cur ^ 1][u]);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int j = j0 + u;
+            const double d = body.use(j, buf[cur][u]);
+            if constexpr (Body::kDots) {
+                dots[j % RG] = d;
+                if (j % RG == RG - 1) red->add_group(j - (RG - 1), dots);
+            }
+        }
     }
-    const T mrow = minv[row];
-    FEL_REDUCER(red, NP);
-#pragma unroll 2
-    for (int j = 0; j < NP; j++) {
+}
+
+#define FEL_ROW_LAYOUT()                                                 \
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x); \
+    const int64_t R = L.R;                                               \
+    const int row = tile * TILE + threadIdx.x
+
+// Row operands shared by the solver bodies: ELL columns and mass values of
+// the row, and (MI) the inverse lumped mass at the columns.
+template <typename T, int W, bool MI>
+struct RowOps {
+    int c[W];
+    T mv[W], mi[MI ? W : 1];
+    T mrow;
+    __device__ __forceinline__ void load(const DevLayout& L, int64_t R, int row) {
+        const T* minv = reinterpret_cast<const T*>(L.minv);
+#pragma unroll
+        for (int k = 0; k < W; k++) {
+            c[k] = L.col[k * R + row];
+            mv[k] = ld<T>(L.Mval, k * R + row);
+            if constexpr (MI) mi[k] = gat(minv, c[k]);
+        }
+        mrow = minv[row];
+    }
+};
+
+// cg_init: X = rhs / m, r = rhs - M X, reduces r.z
+template <typename T, int W, int NP>
+struct CgInitRows {
+    static constexpr bool kDots = true;
+    struct Regs { T g[W]; T own; };
+    RowOps<T, W, true> o;
+    const T* rhs;
+    T *X, *Rv;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* b = rhs + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(b, o.c[k]);
+        r.own = b[row];
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
         T acc = 0;
 #pragma unroll
-        for (int k = 0; k < W; k++) acc += mv[k] * (gat(b, c[k]) * mi[k]);
-        const T bj = gat(b, row);
-        const T r = bj - acc;
-        st<T>(L.X, (int64_t)j * R + row, bj * mrow);
-        st<T>(L.Rv, (int64_t)j * R + row, r);
-        red.add(j, (double)r * (double)r * (double)mrow);
+        for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k]);
+        const T res = r.own - acc;
+        const int64_t i = (int64_t)j * R + row;
+        X[i] = r.own * o.mrow;
+        Rv[i] = res;
+        return (double)res * (double)res * (double)o.mrow;
     }
+};
+
+// cg_a: p_new = r / m + beta p_old (p_old unread on the first iteration),
+// q = M p_new recomputed from neighbour values; reduces p.q -> alpha.
+template <typename T, int W, int NP, bool FIRST>
+struct CgARows {
+    static constexpr bool kDots = true;
+    struct Regs { T g[W]; T h[FIRST ? 1 : W]; T own, ownp; };
+    RowOps<T, W, true> o;
+    const T *Rv, *Pold;
+    T* Pnew;
+    const double* beta;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
+        const T* rv = Rv + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(rv, o.c[k]);
+        r.own = rv[row];
+        if constexpr (!FIRST) {
+            const T* po = Pold + (int64_t)j * R;
+#pragma unroll
+            for (int k = 0; k < W; k++) r.h[k] = gat(po, o.c[k]);
+            r.ownp = po[row];
+        }
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
+        T acc = 0, pown;
+        if constexpr (FIRST) {
+#pragma unroll
+            for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k]);
+            pown = r.own * o.mrow;
+        } else {
+            const T bet = (T)beta[j];
+#pragma unroll
+            for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k] + bet * r.h[k]);
+            pown = r.own * o.mrow + bet * r.ownp;
+        }
+        Pnew[(int64_t)j * R + row] = pown;
+        return (double)pown * (double)acc;
+    }
+};
+
+// cg_b: x += alpha p, r -= alpha M p (M p recomputed), reduces r.z -> beta
+template <typename T, int W, int NP>
+struct CgBRows {
+    static constexpr bool kDots = true;
+    struct Regs { T g[W]; T own, x, r; };
+    RowOps<T, W, false> o;
+    const T* Pn;
+    T *X, *Rv;
+    const double* alpha;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
+        const T* p = Pn + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(p, o.c[k]);
+        r.own = p[row];
+        const int64_t i = (int64_t)j * R + row;
+        r.x = X[i];
+        r.r = Rv[i];
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
+        T qq = 0;
+#pragma unroll
+        for (int k = 0; k < W; k++) qq += o.mv[k] * r.g[k];
+        const T al = (T)alpha[j];
+        const int64_t i = (int64_t)j * R + row;
+        const T res = r.r - al * qq;
+        X[i] = r.x + al * r.own;
+        Rv[i] = res;
+        return (double)res * (double)res * (double)o.mrow;
+    }
+};
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cg_init(DevLayout L, int tile_begin) {
+    FEL_ROW_LAYOUT();
+    CgInitRows<T, W, NP> b;
+    b.o.load(L, R, row);
+    b.rhs = reinterpret_cast<const T*>(L.Pb);
+    b.X = reinterpret_cast<T*>(L.X);
+    b.Rv = reinterpret_cast<T*>(L.Rv);
+    b.R = R;
+    b.row = row;
+    FEL_REDUCER(red, NP);
+    run_rows<NP, CH>(b, &red);
     red.finish(L, tile);
 }
 
-// p_new = r / m + beta p_old (p_old unread on the first iteration),
-// q = M p_new recomputed from neighbour values; reduces p.q -> alpha.
-template <typename T, int W, int NP>
+template <typename T, int W, int NP, int CH>
 __global__ __launch_bounds__(TILE) void k_cg_a(DevLayout L, int tile_begin, int first, int flip) {
-    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    FEL_ROW_LAYOUT();
     const int inst = L.tile_inst[tile];
-    const int64_t R = L.R;
-    const int row = tile * TILE + threadIdx.x;
     const T* Rv = reinterpret_cast<const T*>(L.Rv);
     const T* Pold = reinterpret_cast<const T*>(flip ? L.Pa : L.Pb);
     T* Pnew = reinterpret_cast<T*>(flip ? L.Pb : L.Pa);
-    const T* minv = reinterpret_cast<const T*>(L.minv);
-    int c[W];
-    T mv[W], mi[W];
-#pragma unroll
-    for (int k = 0; k < W; k++) {
-        c[k] = L.col[k * R + row];
-        mv[k] = ld<T>(L.Mval, k * R + row);
-        mi[k] = gat(minv, c[k]);
-    }
-    const T mrow = minv[row];
     FEL_REDUCER(red, NP);
     if (first) {
-#pragma unroll 2
-        for (int j = 0; j < NP; j++) {
-            const T* r = Rv + (int64_t)j * R;
-            T acc = 0;
-#pragma unroll
-            for (int k = 0; k < W; k++) acc += mv[k] * (gat(r, c[k]) * mi[k]);
-            const T pown = gat(r, row) * mrow;
-            Pnew[(int64_t)j * R + row] = pown;
-            red.add(j, (double)pown * (double)acc);
-        }
+        CgARows<T, W, NP, true> b;
+        b.o.load(L, R, row);
+        b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.beta = L.beta + inst * NP, b.R = R, b.row = row;
+        run_rows<NP, CH>(b, &red);
     } else {
-#pragma unroll 2
-        for (int j = 0; j < NP; j++) {
-            const T* r = Rv + (int64_t)j * R;
-            const T* po = Pold + (int64_t)j * R;
-            const T bet = (T)L.beta[inst * NP + j];
-            T acc = 0;
-#pragma unroll
-            for (int k = 0; k < W; k++) acc += mv[k] * (gat(r, c[k]) * mi[k] + bet * gat(po, c[k]));
-            const T pown = gat(r, row) * mrow + bet * gat(po, row);
-            Pnew[(int64_t)j * R + row] = pown;
-            red.add(j, (double)pown * (double)acc);
-        }
+        CgARows<T, W, NP, false> b;
+        b.o.load(L, R, row);
+        b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.beta = L.beta + inst * NP, b.R = R, b.row = row;
+        run_rows<NP, CH>(b, &red);
     }
     red.finish(L, tile);
 }
 
-// x += alpha p, r -= alpha M p (M p recomputed), reduces r.z -> beta;
-template <typename T, int W, int NP>
+template <typename T, int W, int NP, int CH>
 __global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int flip) {
-    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    FEL_ROW_LAYOUT();
     const int inst = L.tile_inst[tile];
-    const int64_t R = L.R;
-    const int row = tile * TILE + threadIdx.x;
-    const T* Pn = reinterpret_cast<const T*>(flip ? L.Pb : L.Pa);
-    T* X = reinterpret_cast<T*>(L.X);
-    T* Rv = reinterpret_cast<T*>(L.Rv);
-    const T* minv = reinterpret_cast<const T*>(L.minv);
-    int c[W];
-    T mv[W];
-#pragma unroll
-    for (int k = 0; k < W; k++) {
-        c[k] = L.col[k * R + row];
-        mv[k] = ld<T>(L.Mval, k * R + row);
-    }
-    const T mrow = minv[row];
+    CgBRows<T, W, NP> b;
+    b.o.load(L, R, row);
+    b.Pn = reinterpret_cast<const T*>(flip ? L.Pb : L.Pa);
+    b.X = reinterpret_cast<T*>(L.X);
+    b.Rv = reinterpret_cast<T*>(L.Rv);
+    b.alpha = L.alpha + inst * NP;
+    b.R = R;
+    b.row = row;
     FEL_REDUCER(red, NP);
-#pragma unroll 2
-    for (int j = 0; j < NP; j++) {
-        const T* p = Pn + (int64_t)j * R;
-        T q = 0;
-#pragma unroll
-        for (int k = 0; k < W; k++) q += mv[k] * gat(p, c[k]);
-        const T al = (T)L.alpha[inst * NP + j];
-        const int64_t i = (int64_t)j * R + row;
-        const T x = X[i] + al * gat(p, row);
-        const T r = Rv[i] - al * q;
-        X[i] = x;
-        Rv[i] = r;
-        red.add(j, (double)r * (double)r * (double)mrow);
-    }
+    run_rows<NP, CH>(b, &red);
     red.finish(L, tile);
 }
 
@@ -371,63 +505,90 @@ __device__ __forceinline__ T* cheb_buf(const DevLayout& L, int b) {
 }
 
 template <typename T, int W, int NP>
-__global__ __launch_bounds__(TILE) void k_cheb_first(DevLayout L, int tile_begin, int out0, T gamma) {
-    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
-    const int64_t R = L.R;
-    const int row = tile * TILE + threadIdx.x;
-    const T* rhs = reinterpret_cast<const T*>(L.Pb);
-    const T* minv = reinterpret_cast<const T*>(L.minv);
-    T* x0 = cheb_buf<T>(L, out0);
-    T* x1 = cheb_buf<T>(L, 1 - out0);
-    int c[W];
-    T mv[W], mi[W];
-#pragma unroll
-    for (int k = 0; k < W; k++) {
-        c[k] = L.col[k * R + row];
-        mv[k] = ld<T>(L.Mval, k * R + row);
-        mi[k] = gat(minv, c[k]);
-    }
-    const T mrow = minv[row];
-#pragma unroll 2
-    for (int j = 0; j < NP; j++) {
+struct ChebFirstRows {
+    static constexpr bool kDots = false;
+    struct Regs { T g[W]; T own; };
+    RowOps<T, W, true> o;
+    const T* rhs;
+    T *x0, *x1;
+    T gamma;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* b = rhs + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(b, o.c[k]);
+        r.own = b[row];
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
         T acc = 0;
 #pragma unroll
-        for (int k = 0; k < W; k++) acc += mv[k] * (gat(b, c[k]) * mi[k]);
-        const T bj = gat(b, row);
-        const T xa = bj * mrow;
-        x0[(int64_t)j * R + row] = xa;
-        x1[(int64_t)j * R + row] = xa + gamma * ((bj - acc) * mrow);
+        for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k]);
+        const T xa = r.own * o.mrow;
+        const int64_t i = (int64_t)j * R + row;
+        x0[i] = xa;
+        x1[i] = xa + gamma * ((r.own - acc) * o.mrow);
+        return 0.0;
     }
-}
+};
 
 template <typename T, int W, int NP>
-__global__ __launch_bounds__(TILE) void k_cheb(DevLayout L, int tile_begin, int cur, T omega, T gamma) {
-    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
-    const int64_t R = L.R;
-    const int row = tile * TILE + threadIdx.x;
-    const T* rhs = reinterpret_cast<const T*>(L.Pb);
-    const T* xk = cheb_buf<T>(L, cur);
-    T* xp = cheb_buf<T>(L, 1 - cur);
-    int c[W];
-    T mv[W];
-#pragma unroll
-    for (int k = 0; k < W; k++) {
-        c[k] = L.col[k * R + row];
-        mv[k] = ld<T>(L.Mval, k * R + row);
-    }
-    const T mrow = ld<T>(L.minv, row);
-#pragma unroll 2
-    for (int j = 0; j < NP; j++) {
+struct ChebRows {
+    static constexpr bool kDots = false;
+    struct Regs { T g[W]; T own, b, xp; };
+    RowOps<T, W, false> o;
+    const T *rhs, *xk;
+    T* xp;
+    T omega, gamma;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* x = xk + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(x, o.c[k]);
+        r.own = x[row];
+        const int64_t i = (int64_t)j * R + row;
+        r.b = rhs[i];
+        r.xp = xp[i];
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
         T acc = 0;
 #pragma unroll
-        for (int k = 0; k < W; k++) acc += mv[k] * gat(x, c[k]);
-        const int64_t i = (int64_t)j * R + row;
-        const T z = (rhs[i] - acc) * mrow;
-        const T xprev = xp[i];
-        xp[i] = omega * (gamma * z + gat(x, row) - xprev) + xprev;
+        for (int k = 0; k < W; k++) acc += o.mv[k] * r.g[k];
+        const T z = (r.b - acc) * o.mrow;
+        xp[(int64_t)j * R + row] = omega * (gamma * z + r.own - r.xp) + r.xp;
+        return 0.0;
     }
+};
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cheb_first(DevLayout L, int tile_begin, int out0, double gamma_d) {
+    FEL_ROW_LAYOUT();
+    ChebFirstRows<T, W, NP> b;
+    b.o.load(L, R, row);
+    b.rhs = reinterpret_cast<const T*>(L.Pb);
+    b.x0 = cheb_buf<T>(L, out0);
+    b.x1 = cheb_buf<T>(L, 1 - out0);
+    b.gamma = (T)gamma_d;
+    b.R = R;
+    b.row = row;
+    run_rows<NP, CH>(b, (TileReducer<NP>*)nullptr);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cheb(DevLayout L, int tile_begin, int cur, double omega_d,
+                                               double gamma_d) {
+    FEL_ROW_LAYOUT();
+    ChebRows<T, W, NP> b;
+    b.o.load(L, R, row);
+    b.rhs = reinterpret_cast<const T*>(L.Pb);
+    b.xk = cheb_buf<T>(L, cur);
+    b.xp = cheb_buf<T>(L, 1 - cur);
+    b.omega = (T)omega_d;
+    b.gamma = (T)gamma_d;
+    b.R = R;
+    b.row = row;
+    run_rows<NP, CH>(b, (TileReducer<NP>*)nullptr);
 }
 
 // lumped-mass approximation: Delta = rhs / m
@@ -1072,33 +1233,44 @@ template <int Q, int W> struct StreamBody {
         FEL_CHECK_LAUNCH();
     }
 };
+// launches kernel K<T, W, NP, CH> for the context's value type and the
+// requested population batch (1, 2 or 4)
+#define FEL_SOLVER_LAUNCH(K, ch, s, nt, ...)                                                     \
+    do {                                                                                        \
+        const bool f64_ = L.precision == 0;                                                     \
+        switch (ch) {                                                                           \
+        case 4:                                                                                 \
+            if (f64_) FEL_LAUNCH((K<double, W, NP, 4>), dim3(nt), dim3(TILE), 0, s, __VA_ARGS__); \
+            else FEL_LAUNCH((K<float, W, NP, 4>), dim3(nt), dim3(TILE), 0, s, __VA_ARGS__);       \
+            break;                                                                              \
+        case 2:                                                                                 \
+            if (f64_) FEL_LAUNCH((K<double, W, NP, 2>), dim3(nt), dim3(TILE), 0, s, __VA_ARGS__); \
+            else FEL_LAUNCH((K<float, W, NP, 2>), dim3(nt), dim3(TILE), 0, s, __VA_ARGS__);       \
+            break;                                                                              \
+        default:                                                                                \
+            if (f64_) FEL_LAUNCH((K<double, W, NP, 1>), dim3(nt), dim3(TILE), 0, s, __VA_ARGS__); \
+            else FEL_LAUNCH((K<float, W, NP, 1>), dim3(nt), dim3(TILE), 0, s, __VA_ARGS__);       \
+        }                                                                                       \
+    } while (0)
+
 template <int Q, int W> struct CgInitBody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int ch, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
-        if (L.precision == 0)
-            FEL_LAUNCH((k_cg_init<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
-        else
-            FEL_LAUNCH((k_cg_init<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        FEL_SOLVER_LAUNCH(k_cg_init, ch, s, nt, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct CgABody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, bool first, bool flip, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, bool first, bool flip, int ch, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
-        if (L.precision == 0)
-            FEL_LAUNCH((k_cg_a<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)first, (int)flip);
-        else
-            FEL_LAUNCH((k_cg_a<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)first, (int)flip);
+        FEL_SOLVER_LAUNCH(k_cg_a, ch, s, nt, L, tb, (int)first, (int)flip);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct CgBBody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, bool flip, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, bool flip, int ch, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
-        if (L.precision == 0)
-            FEL_LAUNCH((k_cg_b<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)flip);
-        else
-            FEL_LAUNCH((k_cg_b<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, (int)flip);
+        FEL_SOLVER_LAUNCH(k_cg_b, ch, s, nt, L, tb, (int)flip);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -1180,14 +1352,14 @@ template <int Q, int W> struct SumsBody {
 hipError_t launch_stream(const DevLayout& L, int tb, int nt, hipStream_t s) {
     return dispatch_qw<StreamBody>(L, tb, nt, s);
 }
-hipError_t launch_cg_init(const DevLayout& L, int tb, int nt, hipStream_t s) {
-    return dispatch_qw<CgInitBody>(L, tb, nt, s);
+hipError_t launch_cg_init(const DevLayout& L, int tb, int nt, int ch, hipStream_t s) {
+    return dispatch_qw<CgInitBody>(L, tb, nt, ch, s);
 }
-hipError_t launch_cg_a(const DevLayout& L, int tb, int nt, bool first, bool flip, hipStream_t s) {
-    return dispatch_qw<CgABody>(L, tb, nt, first, flip, s);
+hipError_t launch_cg_a(const DevLayout& L, int tb, int nt, bool first, bool flip, int ch, hipStream_t s) {
+    return dispatch_qw<CgABody>(L, tb, nt, first, flip, ch, s);
 }
-hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, bool flip, hipStream_t s) {
-    return dispatch_qw<CgBBody>(L, tb, nt, flip, s);
+hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, bool flip, int ch, hipStream_t s) {
+    return dispatch_qw<CgBBody>(L, tb, nt, flip, ch, s);
 }
 hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int np, hipStream_t s) {
     (void)hipGetLastError();
@@ -1202,30 +1374,26 @@ hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op
     return hipGetLastError();
 }
 template <int Q, int W> struct ChebFirstBody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, int out0, double gamma, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int out0, double gamma, int ch, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
-        if (L.precision == 0)
-            FEL_LAUNCH((k_cheb_first<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, out0, gamma);
-        else
-            FEL_LAUNCH((k_cheb_first<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, out0, (float)gamma);
+        FEL_SOLVER_LAUNCH(k_cheb_first, ch, s, nt, L, tb, out0, gamma);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct ChebBody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma, int ch,
+                          hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
-        if (L.precision == 0)
-            FEL_LAUNCH((k_cheb<double, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, cur, omega, gamma);
-        else
-            FEL_LAUNCH((k_cheb<float, W, NP>), dim3(nt), dim3(TILE), 0, s, L, tb, cur, (float)omega, (float)gamma);
+        FEL_SOLVER_LAUNCH(k_cheb, ch, s, nt, L, tb, cur, omega, gamma);
         FEL_CHECK_LAUNCH();
     }
 };
-hipError_t launch_cheb_first(const DevLayout& L, int tb, int nt, int out0, double gamma, hipStream_t s) {
-    return dispatch_qw<ChebFirstBody>(L, tb, nt, out0, gamma, s);
+hipError_t launch_cheb_first(const DevLayout& L, int tb, int nt, int out0, double gamma, int ch, hipStream_t s) {
+    return dispatch_qw<ChebFirstBody>(L, tb, nt, out0, gamma, ch, s);
 }
-hipError_t launch_cheb(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma, hipStream_t s) {
-    return dispatch_qw<ChebBody>(L, tb, nt, cur, omega, gamma, s);
+hipError_t launch_cheb(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma, int ch,
+                       hipStream_t s) {
+    return dispatch_qw<ChebBody>(L, tb, nt, cur, omega, gamma, ch, s);
 }
 
 hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {

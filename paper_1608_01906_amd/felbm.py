@@ -24,13 +24,13 @@ AUX = {"gradrho": 0, "mu": 1, "S": 2, "delta": 3}
 ABI_SYMBOLS = ["fel_create", "fel_upload_mesh", "fel_workspace_size", "fel_bind", "fel_init_fields",
                "fel_step", "fel_sync", "fel_read_fields", "fel_conserved_sums", "fel_get_state",
                "fel_set_state", "fel_read_aux", "fel_profile", "fel_profile_read", "fel_layout_info",
-               "fel_destroy", "fel_last_error", "fel_version"]
+               "fel_tuning", "fel_destroy", "fel_last_error", "fel_version"]
 
 
 class FelOptions(C.Structure):
     _fields_ = [("lattice", C.c_int), ("precision", C.c_int), ("mass_mode", C.c_int), ("cg_iters", C.c_int),
                 ("cg_tol", C.c_double), ("laplacian_mode", C.c_int), ("max_instances", C.c_int),
-                ("node_order", C.c_int)]
+                ("node_order", C.c_int), ("solver_batch", C.c_int)]
 
 
 class FelPhys(C.Structure):
@@ -81,6 +81,7 @@ def load_library():
                                      C.POINTER(C.c_char_p)]
     lib.fel_layout_info.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                     C.POINTER(C.c_int)]
+    lib.fel_tuning.argtypes = [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.fel_destroy.argtypes = [_vp]
     lib.fel_last_error.argtypes = [_vp]
     lib.fel_last_error.restype = C.c_char_p
@@ -109,10 +110,11 @@ class Context:
     """One felbm context: instances uploaded, bound to a torch workspace/stream."""
 
     def __init__(self, lattice: int, *, precision: str = "fp64", mass_mode: int = 0, cg_iters: int = 0,
-                 cg_tol: float = 0.0, laplacian_mode: int = 0, max_instances: int = 1, node_order: int = 0):
+                 cg_tol: float = 0.0, laplacian_mode: int = 0, max_instances: int = 1, node_order: int = 0,
+                 solver_batch: int = 0):
         self.lib = load_library()
         opt = FelOptions(lattice, PREC[precision], mass_mode, cg_iters, cg_tol, laplacian_mode, max_instances,
-                         node_order)
+                         node_order, solver_batch)
         h = _vp()
         st = self.lib.fel_create(C.byref(opt), C.byref(h))
         if st != FEL_OK:
@@ -233,6 +235,14 @@ class Context:
         self._check(self.lib.fel_layout_info(self.h, C.byref(rows), C.byref(w), C.byref(pops), C.byref(it)),
                     "fel_layout_info")
         return dict(rows=rows.value, ell_width=w.value, pops=pops.value, cg_iters=it.value)
+
+    def tuning(self):
+        """Population batch of each kernel class, keyed by class name."""
+        n = C.c_int(0)
+        batch = (C.c_int * 32)()
+        self._check(self.lib.fel_tuning(self.h, 32, C.byref(n), batch), "fel_tuning")
+        names = self.profile_read()
+        return {name: batch[k] for k, name in enumerate(list(names)[:n.value])}
 
 
 def from_workload(workload, *, precision: str = "fp64", device: str = "cuda:0", stream=None, **opts) -> Context:

@@ -35,6 +35,19 @@ def test_bad_options_rejected():
             felbm.Context(9, **kw)
     with pytest.raises(felbm.FelError):
         felbm.Context(7)
+    for nb in (3, 8, -1):
+        with pytest.raises(felbm.FelError):
+            felbm.Context(9, solver_batch=nb)
+
+
+def test_tuning_before_bind():
+    """A fixed solver batch shows on the solver kernels at once; 0 (timed
+    at the first step) reads 0 until then; other kernels read 1."""
+    solver = ("cg_init", "cg_a", "cg_b", "cheb")
+    for nb in (0, 1, 2, 4):
+        t = felbm.Context(19, solver_batch=nb).tuning()
+        assert all(t[k] == nb for k in solver)
+        assert all(v == 1 for k, v in t.items() if k not in solver)
 
 
 def test_inverted_element_rejected():
