@@ -166,7 +166,9 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="chan
                step_algorithmic_gbs=round(step_bytes / (secs / steps) / 1e9, 1),
                step_frac=round(step_bytes / (secs / steps) / 1e9 / HBM_PEAK_GBS, 4),
                kernels=kern,
-               solver_batch={k: v for k, v in ctx.tuning().items() if k in kern},
+               schedule={k: dict(batch=v[0], staging=("direct", "lds")[v[1] - 1])
+                         for k, v in ctx.tuning().items() if k in ("cg_init", "cg_a", "cg_b", "cheb") and k in kern},
+               halo=dict(max=info["halo_max"], mean=round(info["halo_mean"], 1)),
                event_ms_per_step=round(sum(v["total_ms"] for v in kern.values()) / prof_steps, 4))
     return res, ctx
 
@@ -232,7 +234,8 @@ def main():
         "step_algorithmic_gbs": head["step_algorithmic_gbs"],
         "step_frac": head["step_frac"],
         "kernels": head["kernels"],
-        "solver_batch": head["solver_batch"],
+        "schedule": head["schedule"],
+        "halo": head["halo"],
         "event_ms_per_step": head["event_ms_per_step"],
         "status": head["status"],
     }
@@ -246,7 +249,7 @@ def main():
         rch, _ = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, mass_mode=2,
                          workload=args.workload)
         out["chebyshev_solve"] = {k: rch[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
-                                                      "step_frac", "event_ms_per_step", "solver_batch")}
+                                                      "step_frac", "event_ms_per_step", "schedule")}
     if not args.no_cpu_baseline:
         from paper_1608_01906_amd import felbm
         cb, orc, s_steps = cpu_baseline(w)

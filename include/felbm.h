@@ -97,10 +97,17 @@ typedef struct {
                              already coalesced (each neighbour slot of 64 consecutive rows is one
                              contiguous run); unstructured meshes in arbitrary order need the curve.
                              Fields always cross the ABI in the caller's order. */
-    int solver_batch;     /* populations whose neighbour loads a mass-solve kernel issues ahead of
-                             use (its software-pipeline depth): 1, 2 or 4 for every solver kernel, or
-                             0 = chosen per kernel by timing the three on the bound layout before the
-                             first step (results are bit-identical whichever is used) */
+    int solver_batch;     /* populations a mass-solve kernel works on together: with direct gathers
+                             the populations whose neighbour loads it issues ahead of use (its
+                             software-pipeline depth), with LDS staging the populations staged per
+                             pass; 1, 2 or 4 for every solver kernel, or 0 = chosen per kernel by
+                             timing on the bound layout before the first step */
+    int lds_staging;      /* mass-solve kernels read neighbour values 1 = by direct gathers from
+                             memory, 2 = from a per-tile stage in LDS (the tile's rows and its halo
+                             loaded once per population, coalesced), 0 = chosen per kernel by timing.
+                             Every schedule computes the same sums in the same order; results agree
+                             to rounding (the staged and direct forms may contract multiply-adds
+                             differently) */
 } fel_options;
 
 /* Physical parameters of one instance (Section 2.1).  rho_l is the heavy
@@ -195,14 +202,18 @@ FEL_API fel_status fel_profile_read(fel_ctx* ctx, int max_classes, int* n_classe
                                     double* total_ms, const char** names);
 
 /* Sizes of the device layout (for traffic accounting): total padded rows,
- * ELL width, number of stored populations and CG iterations per step. */
-FEL_API fel_status fel_layout_info(fel_ctx* ctx, int64_t* rows, int* ell_width, int* pops, int* cg_iters);
+ * ELL width, number of stored populations, CG iterations per step, and the
+ * largest and mean per-tile halo (columns referenced outside a 256-row
+ * tile).  Any pointer may be NULL. */
+FEL_API fel_status fel_layout_info(fel_ctx* ctx, int64_t* rows, int* ell_width, int* pops, int* cg_iters,
+                                   int* halo_max, double* halo_mean);
 
-/* Population batch in use for each kernel class k < max_classes (same
- * classes and order as fel_profile_read; 1 for the kernels without a
- * tunable batch).  With solver_batch = 0 the solver entries are final after
- * the first fel_step; before it they read 0. */
-FEL_API fel_status fel_tuning(fel_ctx* ctx, int max_classes, int* n_classes, int* batch);
+/* Schedule in use for each kernel class k < max_classes (same classes and
+ * order as fel_profile_read): population batch and staging (1 direct,
+ * 2 LDS-staged); kernels without a tunable schedule read 1.  Values left to
+ * the tuner (option 0) read 0 until the first fel_step.  batch and staging
+ * may be NULL. */
+FEL_API fel_status fel_tuning(fel_ctx* ctx, int max_classes, int* n_classes, int* batch, int* staging);
 
 FEL_API fel_status fel_destroy(fel_ctx* ctx);
 FEL_API const char* fel_last_error(const fel_ctx* ctx);

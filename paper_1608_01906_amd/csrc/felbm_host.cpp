@@ -97,16 +97,23 @@ struct fel_ctx {
     char* dev = nullptr;
     std::vector<int32_t> tile_inst;
     // offsets in the workspace
+    // LDS staging: per-tile halos and local columns (built with the layout)
+    std::vector<int32_t> halo_ptr, halo_col;
+    std::vector<uint16_t> lcol;
+    int hmax = 0, sw = 0;
+    int64_t halo_total = 0;
     struct Off {
-        size_t col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, rho, grad,
+        size_t lcol, halo_ptr, halo_col, col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, rho, grad,
             mu, S, u, p, partial, counter, rz, rz0, alpha, beta, sums, status, end;
     } off{};
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool use_graph = true;
-    // population batch of each kernel class (see run_rows); 0 = not yet tuned
+    // schedule of each kernel class: population batch (see run_rows) and
+    // LDS staging (1 direct gathers, 2 staged); 0 = not yet tuned
     int batch[KC_COUNT] = {};
+    int stage[KC_COUNT] = {};
     // profiling
     bool profiling = false;
     std::vector<ProfEvent> pending;
@@ -203,19 +210,50 @@ uint64_t spread_bits(uint64_t v, int dim) {
     return r;
 }
 
-// Device node order: Z-order (Morton) of the nodes quantised to the mean
-// spacing, so that a wavefront's 64 consecutive rows are a compact patch and
-// the neighbour gathers of a tile stay within a small halo.
-std::vector<int64_t> locality_order(int dim, int64_t n, const double* xyz) {
+// Device node order: Z-order (Morton) of the nodes quantised to the mesh
+// spacing h, so that a wavefront's 64 consecutive rows are a compact patch
+// and a 256-row tile is a block (16 x 16 on a 2-D grid, 8 x 8 x 4 in 3-D)
+// whose halo is its boundary layer.  h is the median, over the element
+// edges that do not wrap around a periodic box, of the significant edge
+// components (those at least half the edge's largest one): on a jittered
+// grid each is one grid step plus symmetric noise, whatever the edge kind
+// (axis, face or body diagonal), so the quantised points fall on the
+// lattice and the Morton blocks align with it.
+std::vector<int64_t> locality_order(int dim, int64_t n, const double* xyz, int64_t n_elems, const int32_t* conn,
+                                    const int8_t* shift) {
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t k = 0; k < n; k++)
         for (int r = 0; r < dim; r++) {
             lo[r] = std::min(lo[r], xyz[k * dim + r]);
             hi[r] = std::max(hi[r], xyz[k * dim + r]);
         }
-    double vol = 1.0;
-    for (int r = 0; r < dim; r++) vol *= std::max(hi[r] - lo[r], 1e-300);
-    const double h = std::pow(vol / (double)n, 1.0 / dim);
+    const int nv = dim + 1;
+    std::vector<double> ext;
+    ext.reserve(n_elems * nv * (nv - 1) / 2);
+    for (int64_t e = 0; e < n_elems; e++) {
+        bool wraps = false;
+        if (shift)
+            for (int i = 0; i < nv * dim; i++) wraps |= shift[e * nv * dim + i] != 0;
+        if (wraps) continue;
+        for (int a = 0; a < nv; a++)
+            for (int b = a + 1; b < nv; b++) {
+                const int64_t p = conn[e * nv + a], q = conn[e * nv + b];
+                double d[3] = {0.0, 0.0, 0.0}, m = 0.0;
+                for (int r = 0; r < dim; r++) m = std::max(m, d[r] = std::fabs(xyz[p * dim + r] - xyz[q * dim + r]));
+                for (int r = 0; r < dim; r++)
+                    if (m > 0.0 && d[r] >= 0.5 * m) ext.push_back(d[r]);
+            }
+    }
+    double h;
+    if (!ext.empty()) {
+        std::nth_element(ext.begin(), ext.begin() + ext.size() / 2, ext.end());
+        h = ext[ext.size() / 2];
+    } else {
+        double vol = 1.0;
+        for (int r = 0; r < dim; r++) vol *= std::max(hi[r] - lo[r], 1e-300);
+        h = std::pow(vol / (double)n, 1.0 / dim);
+    }
+    h = std::max(h, 1e-300);
     const double cap = dim == 2 ? 2147483647.0 : 2097151.0;
     std::vector<uint64_t> key(n);
     for (int64_t k = 0; k < n; k++) {
@@ -255,6 +293,7 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
     if (opt->node_order != FEL_ORDER_CALLER && opt->node_order != FEL_ORDER_ZCURVE) return FEL_EINVAL;
     const int nb = opt->solver_batch;
     if (nb != 0 && nb != 1 && nb != 2 && nb != 4) return FEL_EINVAL;
+    if (opt->lds_staging < 0 || opt->lds_staging > 2) return FEL_EINVAL;
     fel_ctx* c = new (std::nothrow) fel_ctx();
     if (!c) return FEL_ENOMEM;
     c->opt = *opt;
@@ -267,7 +306,11 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
     c->NP = 2 * (opt->lattice - 1);
     c->NB = c->lat.NB;
     for (int k = 0; k < KC_COUNT; k++) c->batch[k] = 1;
-    for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) c->batch[k] = nb;
+    for (int k = 0; k < KC_COUNT; k++) c->stage[k] = 1;
+    for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) {
+        c->batch[k] = nb;
+        c->stage[k] = opt->lds_staging;
+    }
     *out = c;
     return FEL_OK;
 }
@@ -403,7 +446,7 @@ fel_status fel_upload_mesh(fel_ctx* c, int inst, int dim, int64_t n_nodes, const
     // renumber into the device order and assemble there
     std::vector<int64_t> perm;
     if (c->opt.node_order == FEL_ORDER_ZCURVE) {
-        perm = locality_order(dim, n_nodes, xyz);
+        perm = locality_order(dim, n_nodes, xyz, n_elems, conn, shift);
     } else {
         perm.resize(n_nodes);
         for (int64_t k = 0; k < n_nodes; k++) perm[k] = k;
@@ -424,6 +467,62 @@ fel_status fel_upload_mesh(fel_ctx* c, int inst, int dim, int64_t n_nodes, const
     for (int64_t i = 0; i < n_elems * nv; i++) pconn[i] = inv[conn[i]];
     return assemble(c, inst, dim, n_nodes, pxyz.data(), n_elems, pconn.data(), shift, box,
                     wall ? pwall.data() : nullptr, wall ? pwn.data() : nullptr, std::move(perm));
+}
+
+// Per tile: the columns its rows reference outside the tile (the halo,
+// ascending, unique) and every slot column as a tile-local index, so a
+// kernel can stage a tile's neighbourhood in LDS with coalesced own-row
+// loads plus one load per halo entry.  Padding slots and rows reference
+// their own row.
+static void build_halos(fel_ctx* c) {
+    const int64_t R = c->R;
+    const int W = c->W, nt = c->ntiles;
+    c->halo_ptr.assign(nt + 1, 0);
+    c->halo_col.clear();
+    c->lcol.assign((size_t)W * R, 0);
+    for (int64_t r = 0; r < R; r++)
+        for (int k = 0; k < W; k++) c->lcol[k * R + r] = (uint16_t)(r % TILE);
+    c->hmax = 0;
+    std::vector<int32_t> cols;
+    for (int t = 0; t < nt; t++) {
+        c->halo_ptr[t] = (int32_t)c->halo_col.size();
+        const Instance& I = c->inst[c->tile_inst[t]];
+        const HostMesh& hm = I.mesh;
+        const int64_t rb = I.P.row_begin, t0 = (int64_t)t * TILE;
+        cols.clear();
+        for (int64_t r = t0; r < t0 + TILE; r++) {
+            const int64_t k = r - rb;
+            if (k >= hm.N) continue;
+            for (int sl = 0; sl < hm.W; sl++) {
+                const int32_t cl = hm.col[k * hm.W + sl];
+                if (cl < 0) continue;
+                const int64_t g = rb + cl;
+                if (g < t0 || g >= t0 + TILE) cols.push_back((int32_t)g);
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        for (int64_t r = t0; r < t0 + TILE; r++) {
+            const int64_t k = r - rb;
+            if (k >= hm.N) continue;
+            for (int sl = 0; sl < hm.W; sl++) {
+                const int32_t cl = hm.col[k * hm.W + sl];
+                if (cl < 0) continue;
+                const int64_t g = rb + cl;
+                int loc;
+                if (g >= t0 && g < t0 + TILE)
+                    loc = (int)(g - t0);
+                else
+                    loc = TILE + (int)(std::lower_bound(cols.begin(), cols.end(), (int32_t)g) - cols.begin());
+                c->lcol[sl * R + r] = (uint16_t)loc;
+            }
+        }
+        c->hmax = std::max(c->hmax, (int)cols.size());
+        c->halo_col.insert(c->halo_col.end(), cols.begin(), cols.end());
+    }
+    c->halo_ptr[nt] = (int32_t)c->halo_col.size();
+    c->halo_total = (int64_t)c->halo_col.size();
+    c->sw = (TILE + c->hmax + 31) / 32 * 32;
 }
 
 static fel_status plan_layout(fel_ctx* c) {
@@ -453,6 +552,7 @@ static fel_status plan_layout(fel_ctx* c) {
     if (rows >= ((int64_t)1 << 31)) return fail(c, FEL_EINVAL, "too many rows");
     c->R = rows;
     c->ntiles = (int)(rows / TILE);
+    build_halos(c);
     const size_t R = (size_t)rows;
     const int W = c->W, NB = c->NB, NP = c->NP, Q = c->opt.lattice, D = c->lat.D;
     const size_t s = elem_size(c->opt.precision);
@@ -464,6 +564,9 @@ static fel_status plan_layout(fel_ctx* c) {
         return at;
     };
     auto& f = c->off;
+    f.lcol = take(2 * W * R);
+    f.halo_ptr = take(4 * ((size_t)c->ntiles + 1));
+    f.halo_col = take(4 * std::max<size_t>(c->halo_col.size(), 1));
     f.col = take(4 * W * R);
     f.Mval = take(s * W * R);
     f.basis = take(s * NB * W * R);
@@ -548,6 +651,9 @@ static fel_status upload_operators(fel_ctx* c) {
     };
     (void)s;
     HIP_TRY(c, put(c->off.col, col.data(), col.size() * 4));
+    HIP_TRY(c, put(c->off.lcol, c->lcol.data(), c->lcol.size() * 2));
+    HIP_TRY(c, put(c->off.halo_ptr, c->halo_ptr.data(), c->halo_ptr.size() * 4));
+    if (!c->halo_col.empty()) HIP_TRY(c, put(c->off.halo_col, c->halo_col.data(), c->halo_col.size() * 4));
     HIP_TRY(c, put_t(c->off.Mval, Mv));
     HIP_TRY(c, put_t(c->off.basis, basis));
     HIP_TRY(c, put_t(c->off.minv, minv));
@@ -576,6 +682,10 @@ static void set_pointers(fel_ctx* c) {
     L.ntiles = c->ntiles;
     L.precision = c->opt.precision;
     L.col = reinterpret_cast<const int32_t*>(d + f.col);
+    L.lcol = reinterpret_cast<const uint16_t*>(d + f.lcol);
+    L.halo_ptr = reinterpret_cast<const int32_t*>(d + f.halo_ptr);
+    L.halo_col = reinterpret_cast<const int32_t*>(d + f.halo_col);
+    L.sw = c->sw;
     L.Mval = d + f.Mval;
     L.basis = d + f.basis;
     L.minv = d + f.minv;
@@ -628,6 +738,8 @@ fel_status fel_bind(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
         std::vector<double>().swap(hm.basis);
         std::vector<uint32_t>().swap(hm.wmask);
     }
+    std::vector<uint16_t>().swap(c->lcol);
+    std::vector<int32_t>().swap(c->halo_col);
     c->bound = true;
     // graphs cannot be captured on the legacy default stream
     c->use_graph = c->stream != nullptr;
@@ -664,26 +776,34 @@ hipError_t timed(fel_ctx* c, int cls, F&& launch) {
     return e;
 }
 
-hipError_t enqueue_solve(fel_ctx* c, int tb, int nt) {
+// Whether a class runs its LDS-staged kernel, and whether batch ch fits the
+// staged kernel's dynamic LDS (ch stage rows of sw values).
+bool staged(const fel_ctx* c, int cls) { return c->stage[cls] == 2; }
+bool stage_fits(const fel_ctx* c, int ch) {
+    return (size_t)ch * c->sw * (size_t)elem_size(c->opt.precision) <= 60 * 1024;
+}
+
+hipError_t enqueue_solve(fel_ctx* c) {
     const DevLayout& L = c->L;
     hipStream_t s = c->stream;
+    const int tb = 0, nt = c->ntiles;
     hipError_t e;
-    if (c->opt.mass_mode == FEL_MASS_LUMPED) {
-        return timed(c, KC_LUMPED, [&] { return launch_lumped(L, tb, nt, s); });
-    }
+    if (c->opt.mass_mode == FEL_MASS_LUMPED) return timed(c, KC_LUMPED, [&] { return launch_lumped(L, tb, nt, s); });
     if (c->opt.mass_mode == FEL_MASS_CHEBYSHEV) {
         // spectrum of m^-1 M in [1/(d+2), 1]; iterate count cg_iters
         const double a = 1.0 / (c->lat.D + 2), b = 1.0;
         const double theta = 0.5 * (b + a), sigma = (b - a) / (b + a), gamma = 1.0 / theta;
-        const int K = c->cg_iters;
+        const int K = c->cg_iters, ch = c->batch[KC_CHEB];
+        const bool st = staged(c, KC_CHEB);
         const int out0 = (K % 2 == 0) ? 0 : 1;  // x_K must land in buffer 0 (X)
-        if ((e = timed(c, KC_CHEB, [&] { return launch_cheb_first(L, tb, nt, out0, gamma, c->batch[KC_CHEB], s); })) != hipSuccess)
+        if ((e = timed(c, KC_CHEB, [&] { return launch_cheb_first(L, tb, nt, out0, gamma, ch, st, s); })) != hipSuccess)
             return e;
         double omega = 1.0;
         int cur = 1 - out0;  // buffer holding x_1
         for (int k = 1; k < K; k++) {
             omega = (k == 1) ? 1.0 / (1.0 - 0.5 * sigma * sigma) : 1.0 / (1.0 - 0.25 * sigma * sigma * omega);
-            if ((e = timed(c, KC_CHEB, [&] { return launch_cheb(L, tb, nt, cur, omega, gamma, c->batch[KC_CHEB], s); })) != hipSuccess)
+            if ((e = timed(c, KC_CHEB, [&] { return launch_cheb(L, tb, nt, cur, omega, gamma, ch, st, s); })) !=
+                hipSuccess)
                 return e;
             cur = 1 - cur;
         }
@@ -691,69 +811,92 @@ hipError_t enqueue_solve(fel_ctx* c, int tb, int nt) {
     }
     const int ni = c->ninst, np = c->NP;
     auto fin = [&](int op) { return timed(c, KC_FINALIZE, [&] { return launch_finalize(L, 0, ni, op, np, s); }); };
-    if ((e = timed(c, KC_CG_INIT, [&] { return launch_cg_init(L, tb, nt, c->batch[KC_CG_INIT], s); })) != hipSuccess) return e;
+    if ((e = timed(c, KC_CG_INIT, [&] {
+             return launch_cg_init(L, tb, nt, c->batch[KC_CG_INIT], staged(c, KC_CG_INIT), s);
+         })) != hipSuccess)
+        return e;
     if ((e = fin(0)) != hipSuccess) return e;
     for (int it = 0; it < c->cg_iters; it++) {
         const bool flip = (it & 1) != 0;
-        if ((e = timed(c, KC_CG_A, [&] { return launch_cg_a(L, tb, nt, it == 0, flip, c->batch[KC_CG_A], s); })) != hipSuccess)
+        if ((e = timed(c, KC_CG_A, [&] {
+                 return launch_cg_a(L, tb, nt, it == 0, flip, c->batch[KC_CG_A], staged(c, KC_CG_A), s);
+             })) != hipSuccess)
             return e;
         if ((e = fin(1)) != hipSuccess) return e;
-        if ((e = timed(c, KC_CG_B, [&] { return launch_cg_b(L, tb, nt, flip, c->batch[KC_CG_B], s); })) != hipSuccess) return e;
+        if ((e = timed(c, KC_CG_B, [&] {
+                 return launch_cg_b(L, tb, nt, flip, c->batch[KC_CG_B], staged(c, KC_CG_B), s);
+             })) != hipSuccess)
+            return e;
         if ((e = fin(it == c->cg_iters - 1 ? 3 : 2)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// Chooses the population batch of each solver kernel still at 0 (how many
-// populations' loads its pipeline issues ahead) by timing the candidates
-// 1, 2 and 4 on the bound layout.  The launches only touch the
-// solve's scratch vectors (X, Rv, Pa, Pb, tile partials), which the next
-// step's streaming and first solver launch rewrite before reading.
-fel_status tune_batches(fel_ctx* c) {
+// Chooses the schedule of each solver kernel left to the tuner: the
+// population batch (1, 2 or 4: how many populations' loads its pipeline
+// issues ahead, or stages per LDS pass) and direct gathers vs LDS staging,
+// by timing every allowed candidate on the bound layout.  The launches only
+// touch the solve's scratch vectors (X, Rv, Pa, Pb, tile partials), which
+// the next step's streaming and first solver launch rewrite before reading.
+fel_status tune_schedule(fel_ctx* c) {
     const DevLayout& L = c->L;
     hipStream_t s = c->stream;
     const int nt = c->ntiles;
     const double gamma = 2.0 / (1.0 + 1.0 / (c->lat.D + 2));
     hipEvent_t a = get_event(c), b = get_event(c);
     if (!a || !b) return fail(c, FEL_EDEVICE, "event creation failed");
-    auto run = [&](int cls, int t) -> hipError_t {
+    auto run = [&](int cls, int t, bool st) -> hipError_t {
         switch (cls) {
-            case KC_CG_INIT: return launch_cg_init(L, 0, nt, t, s);
-            case KC_CG_A: return launch_cg_a(L, 0, nt, false, false, t, s);
-            case KC_CG_B: return launch_cg_b(L, 0, nt, false, t, s);
-            default: return launch_cheb(L, 0, nt, 1, 1.0, gamma, t, s);
+            case KC_CG_INIT: return launch_cg_init(L, 0, nt, t, st, s);
+            case KC_CG_A: return launch_cg_a(L, 0, nt, false, false, t, st, s);
+            case KC_CG_B: return launch_cg_b(L, 0, nt, false, t, st, s);
+            default: return launch_cheb(L, 0, nt, 1, 1.0, gamma, t, st, s);
         }
     };
-    // kernels the mass mode never launches keep batch 1
+    // kernels the mass mode never launches keep the direct batch-1 form
     const int mode = c->opt.mass_mode;
     for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) {
         const bool used = cls == KC_CHEB ? mode == FEL_MASS_CHEBYSHEV : mode == FEL_MASS_CONSISTENT;
-        if (!used && c->batch[cls] == 0) c->batch[cls] = 1;
+        if (!used) {
+            if (c->batch[cls] == 0) c->batch[cls] = 1;
+            if (c->stage[cls] == 0) c->stage[cls] = 1;
+        }
     }
     constexpr int kWarm = 2, kReps = 8;
     fel_status st = FEL_OK;
     for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) {
-        if (c->batch[cls] != 0) continue;
-        int best = 1;
+        if (c->batch[cls] != 0 && c->stage[cls] != 0) continue;
+        int best_b = 0, best_s = 0;
         float best_ms = 0.0f;
-        for (int t : {1, 2, 4}) {
-            (void)hipGetLastError();
-            hipError_t e = hipSuccess;
-            for (int r = 0; r < kWarm && e == hipSuccess; r++) e = run(cls, t);
-            if (e == hipSuccess) e = hipEventRecord(a, s);
-            for (int r = 0; r < kReps && e == hipSuccess; r++) e = run(cls, t);
-            if (e == hipSuccess) e = hipEventRecord(b, s);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-            if (e != hipSuccess) {
-                st = fail(c, FEL_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e));
-                break;
+        for (int sg : {1, 2}) {
+            if (c->stage[cls] != 0 && c->stage[cls] != sg) continue;
+            for (int t : {1, 2, 4}) {
+                if (c->batch[cls] != 0 && c->batch[cls] != t) continue;
+                if (sg == 2 && !stage_fits(c, t)) continue;
+                (void)hipGetLastError();
+                hipError_t e = hipSuccess;
+                for (int r = 0; r < kWarm && e == hipSuccess; r++) e = run(cls, t, sg == 2);
+                if (e == hipSuccess) e = hipEventRecord(a, s);
+                for (int r = 0; r < kReps && e == hipSuccess; r++) e = run(cls, t, sg == 2);
+                if (e == hipSuccess) e = hipEventRecord(b, s);
+                if (e == hipSuccess) e = hipEventSynchronize(b);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                if (e != hipSuccess) {
+                    st = fail(c, FEL_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e));
+                    break;
+                }
+                if (best_b == 0 || ms < best_ms) best_b = t, best_s = sg, best_ms = ms;
             }
-            if (t == 1 || ms < best_ms) best = t, best_ms = ms;
+            if (st != FEL_OK) break;
         }
         if (st != FEL_OK) break;
-        c->batch[cls] = best;
+        if (best_b == 0) {  // a fixed staged batch whose stage does not fit
+            st = fail(c, FEL_EINVAL, "LDS stage of %d rows of %d values does not fit", c->batch[cls], c->sw);
+            break;
+        }
+        c->batch[cls] = best_b;
+        c->stage[cls] = best_s;
     }
     c->event_pool.push_back(a);
     c->event_pool.push_back(b);
@@ -766,7 +909,7 @@ hipError_t enqueue_step(fel_ctx* c) {
     const int nt = c->ntiles;
     hipError_t e;
     if ((e = timed(c, KC_STREAM, [&] { return launch_stream(L, 0, nt, s); })) != hipSuccess) return e;
-    if ((e = enqueue_solve(c, 0, nt)) != hipSuccess) return e;
+    if ((e = enqueue_solve(c)) != hipSuccess) return e;
     if ((e = timed(c, KC_MOMENTS, [&] { return launch_moments(L, 0, nt, s); })) != hipSuccess) return e;
     if ((e = timed(c, KC_GRAD, [&] { return launch_grad(L, 0, nt, s); })) != hipSuccess) return e;
     if ((e = timed(c, KC_DIV, [&] { return launch_div(L, 0, nt, s); })) != hipSuccess) return e;
@@ -865,8 +1008,10 @@ fel_status fel_step(fel_ctx* c, int n_steps) {
     if (!c || n_steps < 0) return FEL_EINVAL;
     if (!c->bound || !all_initialised(c)) return fail(c, FEL_ESTATE, "step before bind/init_fields");
     if (n_steps == 0) return FEL_OK;
-    if (!c->batch[KC_CG_INIT] || !c->batch[KC_CG_A] || !c->batch[KC_CG_B] || !c->batch[KC_CHEB]) {
-        fel_status st = tune_batches(c);
+    bool untuned = false;
+    for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) untuned |= !c->batch[k] || !c->stage[k];
+    if (untuned) {
+        fel_status st = tune_schedule(c);
         if (st != FEL_OK) return st;
     }
     if (c->profiling || !c->use_graph) {
@@ -1132,7 +1277,8 @@ fel_status fel_profile_read(fel_ctx* c, int max_classes, int* n_classes, int64_t
     return FEL_OK;
 }
 
-fel_status fel_layout_info(fel_ctx* c, int64_t* rows, int* ell_width, int* pops, int* cg_iters) {
+fel_status fel_layout_info(fel_ctx* c, int64_t* rows, int* ell_width, int* pops, int* cg_iters, int* halo_max,
+                           double* halo_mean) {
     if (!c) return FEL_EINVAL;
     if (!c->bound) {
         fel_status st = plan_layout(c);
@@ -1142,14 +1288,18 @@ fel_status fel_layout_info(fel_ctx* c, int64_t* rows, int* ell_width, int* pops,
     if (ell_width) *ell_width = c->W;
     if (pops) *pops = 2 * c->opt.lattice;
     if (cg_iters) *cg_iters = c->opt.mass_mode == FEL_MASS_LUMPED ? 0 : c->cg_iters;
+    if (halo_max) *halo_max = c->hmax;
+    if (halo_mean) *halo_mean = c->ntiles ? (double)c->halo_total / c->ntiles : 0.0;
     return FEL_OK;
 }
 
-fel_status fel_tuning(fel_ctx* c, int max_classes, int* n_classes, int* batch) {
+fel_status fel_tuning(fel_ctx* c, int max_classes, int* n_classes, int* batch, int* staging) {
     if (!c || !n_classes) return FEL_EINVAL;
     *n_classes = KC_COUNT;
-    for (int k = 0; k < KC_COUNT && k < max_classes; k++)
+    for (int k = 0; k < KC_COUNT && k < max_classes; k++) {
         if (batch) batch[k] = c->batch[k];
+        if (staging) staging[k] = c->stage[k];
+    }
     return FEL_OK;
 }
 

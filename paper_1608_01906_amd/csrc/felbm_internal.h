@@ -38,6 +38,13 @@ struct DevLayout {
     const void* minv;      // T [R]   1/m (1 on padding rows)
     const double* mlump;   // double [R] lumped mass (0 on padding rows)
     const uint32_t* wmask; // [R] bit a set: population a takes its opposite after streaming
+    // LDS staging of a tile: its halo (columns outside the tile, ascending)
+    // and the slot columns as tile-local indices (< TILE: own row,
+    // TILE + h: halo entry h); stage rows are `sw` values apart
+    const uint16_t* lcol;       // [W][R]
+    const int32_t* halo_ptr;    // [ntiles + 1]
+    const int32_t* halo_col;    // [halo_ptr[ntiles]]
+    int sw;                     // TILE + largest halo, rounded up to 32
     const int32_t* tile_inst;   // [ntiles]
     const InstParams* params;   // [ninst]
     // populations
@@ -56,7 +63,7 @@ struct DevLayout {
     void* u;               // [dim][R]
     void* p;               // [R]
     // reductions
-    double* partial;       // [ntiles][2(Q-1)] (also reused for the conserved sums)
+    double* partial;       // [2(Q-1)][ntiles] tile partials (also reused for the conserved sums)
     int32_t* counter;      // [ninst]
     double* rz;            // [ninst][2(Q-1)]
     double* rz0;           // [ninst][2(Q-1)]
@@ -93,23 +100,26 @@ struct LaunchEvents {
 };
 extern thread_local LaunchEvents g_launch_events;
 
-// Launchers (felbm_kernels.hip).  tile_begin/ntiles select the tile range;
-// every launcher returns the hipError_t of the launch.
+// Launchers (felbm_kernels.hip, felbm_solver.hip).  tile_begin/ntiles
+// select the tile range; every launcher returns the hipError_t of the launch.
 hipError_t launch_stream(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
-// the solver launchers take the population batch (1, 2 or 4) of their pipeline
-hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, int batch, hipStream_t s);
-hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, bool flip, int batch,
+// The solver launchers take the population batch (1, 2 or 4) of their
+// pipeline or LDS pass and run the LDS-staged kernel when `staged`.
+hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, int batch, bool staged, hipStream_t s);
+hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, bool flip, int batch, bool staged,
                        hipStream_t s);
-hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool flip, int batch, hipStream_t s);
-// op: 0 CG init, 1 alpha, 2 beta, 3 final residual check, 4 conserved sums; np values per tile
-hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int np, hipStream_t s);
+hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool flip, int batch, bool staged,
+                       hipStream_t s);
+// op: 0 CG init, 1 alpha, 2 beta, 3 final residual check, 4 conserved sums;
+// nvals values per tile (partials stored population-major)
+hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int nvals, hipStream_t s);
 hipError_t launch_lumped(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 // Chebyshev solve: first launch writes x_0 to buffer out0 and x_1 to the
 // other (0 = X, 1 = Pa); each later launch reads x_k from buffer cur.
 hipError_t launch_cheb_first(const DevLayout& L, int tile_begin, int ntiles, int out0, double gamma, int batch,
-                             hipStream_t s);
+                             bool staged, hipStream_t s);
 hipError_t launch_cheb(const DevLayout& L, int tile_begin, int ntiles, int cur, double omega, double gamma, int batch,
-                       hipStream_t s);
+                       bool staged, hipStream_t s);
 hipError_t launch_moments(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_grad(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_div(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);

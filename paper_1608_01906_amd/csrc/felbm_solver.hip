@@ -1,0 +1,835 @@
+// Mass-matrix solve of the streaming step (Section 2.2.1): M Delta = rhs for
+// every moving population of every instance, on gfx950.
+//
+//   k_cg_init / k_cg_a / k_cg_b   batched conjugate gradients, lumped
+//                                 preconditioner z = r / m, x0 = rhs / m
+//   k_finalize                    per-instance totals of the tile partials
+//                                 -> CG scalars (fixed summation order)
+//   k_cheb_first / k_cheb         Chebyshev semi-iteration, no reductions
+//   k_lumped                      lumped-mass shortcut Delta = rhs / m
+//
+// Every launch covers the NP = 2(Q - 1) moving populations of all
+// instances.  Vectors are population-major [NP][R]; the per-tile partials
+// are population-major too ([NP][ntiles], so a finalize block reads one
+// contiguous run); the CG scalars are [instance][NP].
+#include "felbm_device.h"
+
+namespace fel {
+
+// What a finalize launch does with the instance totals.
+enum FinOp { FIN_CG_INIT = 0, FIN_CG_A, FIN_CG_B, FIN_CG_LAST, FIN_SUMS };
+
+// One block per (instance, value j = blockIdx.y): sums the instance's tile
+// partials of value j in a fixed order (strided per thread, then wavefront
+// shuffles and the waves in order) and derives the CG scalar (or stores the
+// conserved sum); NP is the stride of the scalar arrays.  The partials of
+// one value are contiguous, so the block's loads are coalesced, and the
+// unrolled strided loop covers instances of up to 8 K tiles (2 M rows) in
+// one round of loads.
+constexpr int FIN_THREADS = 1024;
+
+template <int NP>
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(DevLayout L, int inst_begin, int op) {
+    __shared__ double fin[FIN_THREADS / 64];
+    const int inst = inst_begin + blockIdx.x;
+    const int j = blockIdx.y;
+    const int tb = L.params[inst].tile_begin, nt = L.params[inst].tile_count;
+    const double* src = L.partial + (int64_t)j * L.ntiles + tb;
+    double s = 0.0;
+#pragma unroll 8
+    for (int t = threadIdx.x; t < nt; t += FIN_THREADS) s += src[t];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) fin[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < FIN_THREADS / 64; w++) tot += fin[w];
+    const int i = inst * NP + j;
+    switch (op) {
+    case FIN_CG_INIT:
+        L.rz[i] = tot;
+        L.rz0[i] = tot;
+        L.beta[i] = 0.0;
+        break;
+    case FIN_CG_A:
+        L.alpha[i] = (tot != 0.0) ? L.rz[i] / tot : 0.0;
+        break;
+    case FIN_CG_B: {
+        const double rz = L.rz[i];
+        L.beta[i] = (rz != 0.0) ? tot / rz : 0.0;
+        L.rz[i] = tot;
+        break;
+    }
+    case FIN_CG_LAST: {
+        const double r0 = L.rz0[i];
+        if (r0 > 0.0 && !(tot <= L.cg_tol2 * r0)) atomicOr(L.status, 2u);
+        break;
+    }
+    case FIN_SUMS:
+        L.sums[inst * 8 + j] = tot;
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Thread layout of the solver kernels: one thread per row, a block covers
+// one tile of TILE rows, so every wavefront load is 64 consecutive rows of
+// one population.  Each kernel walks the NP populations as a two-stage
+// software pipeline (run_rows): the loads of the next batch of CH
+// populations (neighbour gathers and own-row values) are issued before the
+// current batch is used, so a wave has up to 2 CH populations' loads in
+// flight.  CH (1, 2 or 4) is chosen per kernel by the autotuner.  A batch
+// only writes its own populations' rows and only reads populations or
+// buffers that the launch does not write, so the early loads are safe.
+// The FP64 dot products are reduced RG populations at a time.
+constexpr int RG = 4;
+
+template <int NP, int CH, class Body>
+__device__ __forceinline__ void run_rows(Body& body, TileReducer<NP>* red) {
+    static_assert(NP % CH == 0 && NP % RG == 0, "population batches must tile NP");
+    typename Body::Regs buf[2][CH];
+#pragma unroll
+    for (int u = 0; u < CH; u++) body.load(u, buf[0][u]);
+    double dots[RG];
+#pragma unroll
+    for (int j0 = 0; j0 < NP; j0 += CH) {
+        const int cur = (j0 / CH) & 1;
+        if (j0 + CH < NP) {
+#pragma unroll
+            for (int u = 0; u < CH; u++) body.load(j0 + CH + u, buf[cur ^ 1][u]);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int j = j0 + u;
+            const double d = body.use(j, buf[cur][u]);
+            if constexpr (Body::kDots) {
+                dots[j % RG] = d;
+                if (j % RG == RG - 1) red->add_group(j - (RG - 1), dots);
+            }
+        }
+    }
+}
+
+#define FEL_ROW_LAYOUT()                                                 \
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x); \
+    const int64_t R = L.R;                                               \
+    const int row = tile * TILE + threadIdx.x
+
+// Row operands shared by the solver bodies: ELL columns and mass values of
+// the row, and (MI) the inverse lumped mass at the columns.
+template <typename T, int W, bool MI>
+struct RowOps {
+    int c[W];
+    T mv[W], mi[MI ? W : 1];
+    T mrow;
+    __device__ __forceinline__ void load(const DevLayout& L, int64_t R, int row) {
+        const T* minv = reinterpret_cast<const T*>(L.minv);
+#pragma unroll
+        for (int k = 0; k < W; k++) {
+            c[k] = L.col[k * R + row];
+            mv[k] = ld<T>(L.Mval, k * R + row);
+            if constexpr (MI) mi[k] = gat(minv, c[k]);
+        }
+        mrow = minv[row];
+    }
+};
+
+// cg_init: X = rhs / m, r = rhs - M X, reduces r.z
+template <typename T, int W>
+struct CgInitRows {
+    static constexpr bool kDots = true;
+    struct Regs { T g[W]; T own; };
+    RowOps<T, W, true> o;
+    const T* rhs;
+    T *X, *Rv;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
+        const T* b = rhs + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(b, o.c[k]);
+        r.own = b[row];
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k]);
+        const T res = r.own - acc;
+        const int64_t i = (int64_t)j * R + row;
+        X[i] = r.own * o.mrow;
+        Rv[i] = res;
+        return (double)res * (double)res * (double)o.mrow;
+    }
+};
+
+// cg_a: p_new = r / m + beta p_old (p_old unread on the first iteration),
+// q = M p_new recomputed from neighbour values; reduces p.q -> alpha.
+template <typename T, int W, bool FIRST>
+struct CgARows {
+    static constexpr bool kDots = true;
+    struct Regs { T g[W]; T h[FIRST ? 1 : W]; T own, ownp; };
+    RowOps<T, W, true> o;
+    const T *Rv, *Pold;
+    T* Pnew;
+    const double* beta;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
+        const T* rv = Rv + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(rv, o.c[k]);
+        r.own = rv[row];
+        if constexpr (!FIRST) {
+            const T* po = Pold + (int64_t)j * R;
+#pragma unroll
+            for (int k = 0; k < W; k++) r.h[k] = gat(po, o.c[k]);
+            r.ownp = po[row];
+        }
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
+        T acc = 0, pown;
+        if constexpr (FIRST) {
+#pragma unroll
+            for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k]);
+            pown = r.own * o.mrow;
+        } else {
+            const T bet = (T)beta[j];
+#pragma unroll
+            for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k] + bet * r.h[k]);
+            pown = r.own * o.mrow + bet * r.ownp;
+        }
+        Pnew[(int64_t)j * R + row] = pown;
+        return (double)pown * (double)acc;
+    }
+};
+
+// cg_b: x += alpha p, r -= alpha M p (M p recomputed), reduces r.z -> beta
+template <typename T, int W>
+struct CgBRows {
+    static constexpr bool kDots = true;
+    struct Regs { T g[W]; T own, x, r; };
+    RowOps<T, W, false> o;
+    const T* Pn;
+    T *X, *Rv;
+    const double* alpha;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
+        const T* p = Pn + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(p, o.c[k]);
+        r.own = p[row];
+        const int64_t i = (int64_t)j * R + row;
+        r.x = X[i];
+        r.r = Rv[i];
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
+        T qq = 0;
+#pragma unroll
+        for (int k = 0; k < W; k++) qq += o.mv[k] * r.g[k];
+        const T al = (T)alpha[j];
+        const int64_t i = (int64_t)j * R + row;
+        const T res = r.r - al * qq;
+        X[i] = r.x + al * r.own;
+        Rv[i] = res;
+        return (double)res * (double)res * (double)o.mrow;
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ T* vec(void* base) {
+    return reinterpret_cast<T*>(base);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cg_init(DevLayout L, int tile_begin) {
+    FEL_ROW_LAYOUT();
+    CgInitRows<T, W> b;
+    b.o.load(L, R, row);
+    b.rhs = vec<T>(L.Pb);
+    b.X = vec<T>(L.X);
+    b.Rv = vec<T>(L.Rv);
+    b.R = R;
+    b.row = row;
+    FEL_REDUCER(red, NP);
+    run_rows<NP, CH>(b, &red);
+    red.finish(L, tile);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cg_a(DevLayout L, int tile_begin, int first, int flip) {
+    FEL_ROW_LAYOUT();
+    const int inst = L.tile_inst[tile];
+    const T* Rv = vec<T>(L.Rv);
+    const T* Pold = vec<T>(flip ? L.Pa : L.Pb);
+    T* Pnew = vec<T>(flip ? L.Pb : L.Pa);
+    const double* beta = L.beta + inst * NP;
+    FEL_REDUCER(red, NP);
+    if (first) {
+        CgARows<T, W, true> b;
+        b.o.load(L, R, row);
+        b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.beta = beta, b.R = R, b.row = row;
+        run_rows<NP, CH>(b, &red);
+    } else {
+        CgARows<T, W, false> b;
+        b.o.load(L, R, row);
+        b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.beta = beta, b.R = R, b.row = row;
+        run_rows<NP, CH>(b, &red);
+    }
+    red.finish(L, tile);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int flip) {
+    FEL_ROW_LAYOUT();
+    const int inst = L.tile_inst[tile];
+    CgBRows<T, W> b;
+    b.o.load(L, R, row);
+    b.Pn = vec<T>(flip ? L.Pb : L.Pa);
+    b.X = vec<T>(L.X);
+    b.Rv = vec<T>(L.Rv);
+    b.alpha = L.alpha + inst * NP;
+    b.R = R;
+    b.row = row;
+    FEL_REDUCER(red, NP);
+    run_rows<NP, CH>(b, &red);
+    red.finish(L, tile);
+}
+
+// Chebyshev semi-iteration on M Delta = rhs, preconditioned by the lumped
+// mass, with the a-priori spectrum bounds of m^-1 M ([1/(d+2), 1] for P1
+// simplices, element by element):
+//   x_0 = rhs / m,   x_1 = x_0 + gamma z_0,
+//   x_{k+1} = omega_{k+1} (gamma z_k + x_k - x_{k-1}) + x_{k-1},
+//   z_k = m^-1 (rhs - M x_k).
+// No inner products, so no reductions; sum m x is conserved at every iterate
+// (sum m z_k = 0).  The two iterates live in buf 0 = X and buf 1 = Pa; a
+// launch reads x_k (gathered) and x_{k-1} (own row) and overwrites x_{k-1}.
+template <typename T>
+__device__ __forceinline__ T* cheb_buf(const DevLayout& L, int b) {
+    return reinterpret_cast<T*>(b ? L.Pa : L.X);
+}
+
+template <typename T, int W>
+struct ChebFirstRows {
+    static constexpr bool kDots = false;
+    struct Regs { T g[W]; T own; };
+    RowOps<T, W, true> o;
+    const T* rhs;
+    T *x0, *x1;
+    T gamma;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
+        const T* b = rhs + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(b, o.c[k]);
+        r.own = b[row];
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k]);
+        const T xa = r.own * o.mrow;
+        const int64_t i = (int64_t)j * R + row;
+        x0[i] = xa;
+        x1[i] = xa + gamma * ((r.own - acc) * o.mrow);
+        return 0.0;
+    }
+};
+
+template <typename T, int W>
+struct ChebRows {
+    static constexpr bool kDots = false;
+    struct Regs { T g[W]; T own, b, xp; };
+    RowOps<T, W, false> o;
+    const T *rhs, *xk;
+    T* xp;
+    T omega, gamma;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
+        const T* x = xk + (int64_t)j * R;
+#pragma unroll
+        for (int k = 0; k < W; k++) r.g[k] = gat(x, o.c[k]);
+        r.own = x[row];
+        const int64_t i = (int64_t)j * R + row;
+        r.b = rhs[i];
+        r.xp = xp[i];
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < W; k++) acc += o.mv[k] * r.g[k];
+        const T z = (r.b - acc) * o.mrow;
+        xp[(int64_t)j * R + row] = omega * (gamma * z + r.own - r.xp) + r.xp;
+        return 0.0;
+    }
+};
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cheb_first(DevLayout L, int tile_begin, int out0,
+                                                     double gamma_d) {
+    FEL_ROW_LAYOUT();
+    ChebFirstRows<T, W> b;
+    b.o.load(L, R, row);
+    b.rhs = vec<T>(L.Pb);
+    b.x0 = cheb_buf<T>(L, out0);
+    b.x1 = cheb_buf<T>(L, 1 - out0);
+    b.gamma = (T)gamma_d;
+    b.R = R;
+    b.row = row;
+    run_rows<NP, CH>(b, (TileReducer<NP>*)nullptr);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cheb(DevLayout L, int tile_begin, int cur, double omega_d,
+                                               double gamma_d) {
+    FEL_ROW_LAYOUT();
+    ChebRows<T, W> b;
+    b.o.load(L, R, row);
+    b.rhs = vec<T>(L.Pb);
+    b.xk = cheb_buf<T>(L, cur);
+    b.xp = cheb_buf<T>(L, 1 - cur);
+    b.omega = (T)omega_d;
+    b.gamma = (T)gamma_d;
+    b.R = R;
+    b.row = row;
+    run_rows<NP, CH>(b, (TileReducer<NP>*)nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged variants.  A pass stages, for CH populations, the value every
+// row of the tile and every halo entry contributes to the M-product (own
+// rows with coalesced loads, the halo with one load per entry, values the
+// same expression the direct kernels apply to their gathers), then each
+// row reads its W neighbours from LDS through the 16-bit local columns.
+// A wavefront thus issues 1 + halo/TILE global loads per population and
+// vector instead of W gathers.  CH populations per pass, rows sw apart.
+
+template <int W>
+struct LocalCols {
+    int lc[W];
+    __device__ __forceinline__ void load(const DevLayout& L, int64_t R, int row) {
+#pragma unroll
+        for (int k = 0; k < W; k++) lc[k] = L.lcol[k * R + row];
+    }
+};
+
+// sum_k mv[k] * stage[lc[k]]
+template <typename T, int W>
+__device__ __forceinline__ T lds_row_product(const T* mv, const LocalCols<W>& l, const T* stage) {
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < W; k++) acc += mv[k] * stage[l.lc[k]];
+    return acc;
+}
+
+// Drives the passes: body.stage(j, g) is the staged value of population j
+// at global row g; body.keep(j, own) loads what the row keeps in registers
+// for population j; body.use(j, stage_row, own) finishes the row and
+// returns its dot-product term.
+template <typename T, int NP, int CH, class Body>
+__device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int tile, int row, T* sh,
+                                           TileReducer<NP>* red) {
+    static_assert(NP % CH == 0 && NP % RG == 0, "population passes must tile NP");
+    const int sw = L.sw;
+    const int hb = L.halo_ptr[tile], hn = L.halo_ptr[tile + 1] - hb;
+    const int lr = threadIdx.x;
+    double dots[RG];
+#pragma unroll
+    for (int j0 = 0; j0 < NP; j0 += CH) {
+        typename Body::Own own[CH];
+        T v[CH];
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            body.keep(j0 + u, own[u]);
+            v[u] = body.stage(j0 + u, row);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; u++) sh[u * sw + lr] = v[u];
+        for (int h = lr; h < hn; h += TILE) {
+            const int g = L.halo_col[hb + h];
+#pragma unroll
+            for (int u = 0; u < CH; u++) v[u] = body.stage(j0 + u, g);
+#pragma unroll
+            for (int u = 0; u < CH; u++) sh[u * sw + TILE + h] = v[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int j = j0 + u;
+            const double d = body.use(j, sh + u * sw, own[u]);
+            if constexpr (Body::kDots) {
+                dots[j % RG] = d;
+                if (j % RG == RG - 1) red->add_group(j - (RG - 1), dots);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// cg_init staged: stage rhs / m
+template <typename T, int W>
+struct CgInitStaged {
+    static constexpr bool kDots = true;
+    struct Own { T rhs; };
+    LocalCols<W> l;
+    T mv[W], mrow;
+    const T *rhs, *minv;
+    T *X, *Rv;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ T stage(int j, int g) const { return rhs[(int64_t)j * R + g] * minv[g]; }
+    __device__ __forceinline__ void keep(int j, Own& o) const { o.rhs = rhs[(int64_t)j * R + row]; }
+    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
+        const T acc = lds_row_product<T, W>(mv, l, st);
+        const T res = o.rhs - acc;
+        const int64_t i = (int64_t)j * R + row;
+        X[i] = o.rhs * mrow;
+        Rv[i] = res;
+        return (double)res * (double)res * (double)mrow;
+    }
+};
+
+// cg_a staged: stage p_new = r / m + beta p_old
+template <typename T, int W, bool FIRST>
+struct CgAStaged {
+    static constexpr bool kDots = true;
+    struct Own {};
+    LocalCols<W> l;
+    T mv[W];
+    const T *Rv, *Pold, *minv;
+    T* Pnew;
+    const double* beta;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ T stage(int j, int g) const {
+        const int64_t i = (int64_t)j * R + g;
+        if constexpr (FIRST)
+            return Rv[i] * minv[g];
+        else
+            return Rv[i] * minv[g] + (T)beta[j] * Pold[i];
+    }
+    __device__ __forceinline__ void keep(int, Own&) const {}
+    __device__ __forceinline__ double use(int j, const T* st, const Own&) const {
+        const T acc = lds_row_product<T, W>(mv, l, st);
+        const T pown = st[threadIdx.x];
+        Pnew[(int64_t)j * R + row] = pown;
+        return (double)pown * (double)acc;
+    }
+};
+
+// cg_b staged: stage p
+template <typename T, int W>
+struct CgBStaged {
+    static constexpr bool kDots = true;
+    struct Own { T x, r; };
+    LocalCols<W> l;
+    T mv[W], mrow;
+    const T* Pn;
+    T *X, *Rv;
+    const double* alpha;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ T stage(int j, int g) const { return Pn[(int64_t)j * R + g]; }
+    __device__ __forceinline__ void keep(int j, Own& o) const {
+        const int64_t i = (int64_t)j * R + row;
+        o.x = X[i];
+        o.r = Rv[i];
+    }
+    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
+        const T qq = lds_row_product<T, W>(mv, l, st);
+        const T al = (T)alpha[j];
+        const int64_t i = (int64_t)j * R + row;
+        const T res = o.r - al * qq;
+        X[i] = o.x + al * st[threadIdx.x];
+        Rv[i] = res;
+        return (double)res * (double)res * (double)mrow;
+    }
+};
+
+// Chebyshev first iterate staged: stage rhs / m
+template <typename T, int W>
+struct ChebFirstStaged {
+    static constexpr bool kDots = false;
+    struct Own { T rhs; };
+    LocalCols<W> l;
+    T mv[W], mrow;
+    const T *rhs, *minv;
+    T *x0, *x1;
+    T gamma;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ T stage(int j, int g) const { return rhs[(int64_t)j * R + g] * minv[g]; }
+    __device__ __forceinline__ void keep(int j, Own& o) const { o.rhs = rhs[(int64_t)j * R + row]; }
+    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
+        const T acc = lds_row_product<T, W>(mv, l, st);
+        const T xa = o.rhs * mrow;
+        const int64_t i = (int64_t)j * R + row;
+        x0[i] = xa;
+        x1[i] = xa + gamma * ((o.rhs - acc) * mrow);
+        return 0.0;
+    }
+};
+
+// Chebyshev iterate staged: stage x_k
+template <typename T, int W>
+struct ChebStaged {
+    static constexpr bool kDots = false;
+    struct Own { T b, xp; };
+    LocalCols<W> l;
+    T mv[W], mrow;
+    const T *rhs, *xk;
+    T* xp;
+    T omega, gamma;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ T stage(int j, int g) const { return xk[(int64_t)j * R + g]; }
+    __device__ __forceinline__ void keep(int j, Own& o) const {
+        const int64_t i = (int64_t)j * R + row;
+        o.b = rhs[i];
+        o.xp = xp[i];
+    }
+    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
+        const T acc = lds_row_product<T, W>(mv, l, st);
+        const T z = (o.b - acc) * mrow;
+        xp[(int64_t)j * R + row] = omega * (gamma * z + st[threadIdx.x] - o.xp) + o.xp;
+        return 0.0;
+    }
+};
+
+template <typename T, int W, class B>
+__device__ __forceinline__ void staged_row_setup(B& b, const DevLayout& L, int64_t R, int row) {
+    b.l.load(L, R, row);
+#pragma unroll
+    for (int k = 0; k < W; k++) b.mv[k] = ld<T>(L.Mval, k * R + row);
+    b.R = R;
+    b.row = row;
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cg_init_lds(DevLayout L, int tile_begin) {
+    FEL_ROW_LAYOUT();
+    extern __shared__ __align__(16) unsigned char fel_smem[];
+    CgInitStaged<T, W> b;
+    staged_row_setup<T, W>(b, L, R, row);
+    b.minv = reinterpret_cast<const T*>(L.minv);
+    b.mrow = b.minv[row];
+    b.rhs = vec<T>(L.Pb);
+    b.X = vec<T>(L.X);
+    b.Rv = vec<T>(L.Rv);
+    FEL_REDUCER(red, NP);
+    run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
+    red.finish(L, tile);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, int first, int flip) {
+    FEL_ROW_LAYOUT();
+    extern __shared__ __align__(16) unsigned char fel_smem[];
+    const int inst = L.tile_inst[tile];
+    T* sh = reinterpret_cast<T*>(fel_smem);
+    FEL_REDUCER(red, NP);
+    auto setup = [&](auto& b) {
+        staged_row_setup<T, W>(b, L, R, row);
+        b.minv = reinterpret_cast<const T*>(L.minv);
+        b.Rv = vec<T>(L.Rv);
+        b.Pold = vec<T>(flip ? L.Pa : L.Pb);
+        b.Pnew = vec<T>(flip ? L.Pb : L.Pa);
+        b.beta = L.beta + inst * NP;
+    };
+    if (first) {
+        CgAStaged<T, W, true> b;
+        setup(b);
+        run_staged<T, NP, CH>(b, L, tile, row, sh, &red);
+    } else {
+        CgAStaged<T, W, false> b;
+        setup(b);
+        run_staged<T, NP, CH>(b, L, tile, row, sh, &red);
+    }
+    red.finish(L, tile);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, int flip) {
+    FEL_ROW_LAYOUT();
+    extern __shared__ __align__(16) unsigned char fel_smem[];
+    const int inst = L.tile_inst[tile];
+    CgBStaged<T, W> b;
+    staged_row_setup<T, W>(b, L, R, row);
+    b.mrow = ld<T>(L.minv, row);
+    b.Pn = vec<T>(flip ? L.Pb : L.Pa);
+    b.X = vec<T>(L.X);
+    b.Rv = vec<T>(L.Rv);
+    b.alpha = L.alpha + inst * NP;
+    FEL_REDUCER(red, NP);
+    run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
+    red.finish(L, tile);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cheb_first_lds(DevLayout L, int tile_begin, int out0,
+                                                         double gamma_d) {
+    FEL_ROW_LAYOUT();
+    extern __shared__ __align__(16) unsigned char fel_smem[];
+    ChebFirstStaged<T, W> b;
+    staged_row_setup<T, W>(b, L, R, row);
+    b.minv = reinterpret_cast<const T*>(L.minv);
+    b.mrow = b.minv[row];
+    b.rhs = vec<T>(L.Pb);
+    b.x0 = cheb_buf<T>(L, out0);
+    b.x1 = cheb_buf<T>(L, 1 - out0);
+    b.gamma = (T)gamma_d;
+    run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), (TileReducer<NP>*)nullptr);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(TILE) void k_cheb_lds(DevLayout L, int tile_begin, int cur, double omega_d,
+                                                   double gamma_d) {
+    FEL_ROW_LAYOUT();
+    extern __shared__ __align__(16) unsigned char fel_smem[];
+    ChebStaged<T, W> b;
+    staged_row_setup<T, W>(b, L, R, row);
+    b.mrow = ld<T>(L.minv, row);
+    b.rhs = vec<T>(L.Pb);
+    b.xk = cheb_buf<T>(L, cur);
+    b.xp = cheb_buf<T>(L, 1 - cur);
+    b.omega = (T)omega_d;
+    b.gamma = (T)gamma_d;
+    run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), (TileReducer<NP>*)nullptr);
+}
+
+// lumped-mass approximation: Delta = rhs / m
+template <typename T, int NP>
+__global__ __launch_bounds__(TILE) void k_lumped(DevLayout L, int tile_begin) {
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    const int64_t R = L.R;
+    const int64_t row = (int64_t)tile * TILE + threadIdx.x;
+    const T mrow = ld<T>(L.minv, row);
+#pragma unroll 4
+    for (int j = 0; j < NP; j++) st<T>(L.X, (int64_t)j * R + row, ld<T>(L.Pb, (int64_t)j * R + row) * mrow);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+
+// dynamic LDS a staged launch may use
+constexpr size_t kMaxStageBytes = 60 * 1024;  // plus the static reducer buffer
+
+// Launches kernel K<T, W, NP, CH> (or, when staged, K_lds with ch * sw
+// values of dynamic LDS) for the context's value type and the population
+// batch ch (1, 2 or 4).
+#define FEL_SOLVER_LAUNCH_T(K, T, SH, ch, s, nt, ...)                                    \
+    do {                                                                               \
+        switch (ch) {                                                                  \
+        case 4: FEL_LAUNCH((K<T, W, NP, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); break; \
+        case 2: FEL_LAUNCH((K<T, W, NP, 2>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); break; \
+        default: FEL_LAUNCH((K<T, W, NP, 1>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);       \
+        }                                                                              \
+    } while (0)
+
+#define FEL_SOLVER_LAUNCH(K, ch, staged, s, nt, ...)                                   \
+    do {                                                                              \
+        const bool f64_ = L.precision == 0;                                           \
+        if (staged) {                                                                 \
+            const size_t sh_ = (size_t)(ch) * L.sw * (f64_ ? 8 : 4);                  \
+            if (sh_ > kMaxStageBytes) return hipErrorInvalidValue;                    \
+            if (f64_) FEL_SOLVER_LAUNCH_T(K##_lds, double, sh_, ch, s, nt, __VA_ARGS__); \
+            else FEL_SOLVER_LAUNCH_T(K##_lds, float, sh_, ch, s, nt, __VA_ARGS__);       \
+        } else {                                                                      \
+            if (f64_) FEL_SOLVER_LAUNCH_T(K, double, 0, ch, s, nt, __VA_ARGS__);          \
+            else FEL_SOLVER_LAUNCH_T(K, float, 0, ch, s, nt, __VA_ARGS__);                \
+        }                                                                             \
+    } while (0)
+
+template <int Q, int W> struct CgInitBody {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int ch, bool st, hipStream_t s) {
+        constexpr int NP = 2 * (Q - 1);
+        FEL_SOLVER_LAUNCH(k_cg_init, ch, st, s, nt, L, tb);
+        FEL_CHECK_LAUNCH();
+    }
+};
+template <int Q, int W> struct CgABody {
+    static hipError_t run(const DevLayout& L, int tb, int nt, bool first, bool flip, int ch,
+                          bool st, hipStream_t s) {
+        constexpr int NP = 2 * (Q - 1);
+        FEL_SOLVER_LAUNCH(k_cg_a, ch, st, s, nt, L, tb, (int)first, (int)flip);
+        FEL_CHECK_LAUNCH();
+    }
+};
+template <int Q, int W> struct CgBBody {
+    static hipError_t run(const DevLayout& L, int tb, int nt, bool flip, int ch, bool st,
+                          hipStream_t s) {
+        constexpr int NP = 2 * (Q - 1);
+        FEL_SOLVER_LAUNCH(k_cg_b, ch, st, s, nt, L, tb, (int)flip);
+        FEL_CHECK_LAUNCH();
+    }
+};
+template <int Q, int W> struct ChebFirstBody {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int out0, double gamma, int ch,
+                          bool st, hipStream_t s) {
+        constexpr int NP = 2 * (Q - 1);
+        FEL_SOLVER_LAUNCH(k_cheb_first, ch, st, s, nt, L, tb, out0, gamma);
+        FEL_CHECK_LAUNCH();
+    }
+};
+template <int Q, int W> struct ChebBody {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma,
+                          int ch, bool st, hipStream_t s) {
+        constexpr int NP = 2 * (Q - 1);
+        FEL_SOLVER_LAUNCH(k_cheb, ch, st, s, nt, L, tb, cur, omega, gamma);
+        FEL_CHECK_LAUNCH();
+    }
+};
+template <int Q, int W> struct LumpedBody {
+    static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
+        constexpr int NP = 2 * (Q - 1);
+        if (L.precision == 0)
+            FEL_LAUNCH((k_lumped<double, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        else
+            FEL_LAUNCH((k_lumped<float, NP>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        FEL_CHECK_LAUNCH();
+    }
+};
+
+hipError_t launch_cg_init(const DevLayout& L, int tb, int nt, int batch, bool staged,
+                          hipStream_t s) {
+    return dispatch_qw<CgInitBody>(L, tb, nt, batch, staged, s);
+}
+hipError_t launch_cg_a(const DevLayout& L, int tb, int nt, bool first, bool flip, int batch,
+                       bool staged, hipStream_t s) {
+    return dispatch_qw<CgABody>(L, tb, nt, first, flip, batch, staged, s);
+}
+hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, bool flip, int batch, bool staged,
+                       hipStream_t s) {
+    return dispatch_qw<CgBBody>(L, tb, nt, flip, batch, staged, s);
+}
+hipError_t launch_cheb_first(const DevLayout& L, int tb, int nt, int out0, double gamma, int batch,
+                             bool staged, hipStream_t s) {
+    return dispatch_qw<ChebFirstBody>(L, tb, nt, out0, gamma, batch, staged, s);
+}
+hipError_t launch_cheb(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma,
+                       int batch, bool staged, hipStream_t s) {
+    return dispatch_qw<ChebBody>(L, tb, nt, cur, omega, gamma, batch, staged, s);
+}
+hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {
+    return dispatch_qw<LumpedBody>(L, tb, nt, s);
+}
+
+hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int nvals, hipStream_t s) {
+    (void)hipGetLastError();
+    const dim3 grid(ninst, nvals), block(FIN_THREADS);
+    if (nvals == 16)
+        FEL_LAUNCH((k_finalize<16>), grid, block, 0, s, L, inst_begin, op);
+    else if (nvals == 36)
+        FEL_LAUNCH((k_finalize<36>), grid, block, 0, s, L, inst_begin, op);
+    else if (nvals == 8)
+        FEL_LAUNCH((k_finalize<8>), grid, block, 0, s, L, inst_begin, op);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace fel

@@ -38,16 +38,37 @@ def test_bad_options_rejected():
     for nb in (3, 8, -1):
         with pytest.raises(felbm.FelError):
             felbm.Context(9, solver_batch=nb)
+    for sg in (3, -1):
+        with pytest.raises(felbm.FelError):
+            felbm.Context(9, lds_staging=sg)
 
 
 def test_tuning_before_bind():
-    """A fixed solver batch shows on the solver kernels at once; 0 (timed
-    at the first step) reads 0 until then; other kernels read 1."""
+    """A fixed solver schedule shows on the solver kernels at once; 0 (timed
+    at the first step) reads 0 until then; other kernels read (1, 1)."""
     solver = ("cg_init", "cg_a", "cg_b", "cheb")
     for nb in (0, 1, 2, 4):
-        t = felbm.Context(19, solver_batch=nb).tuning()
-        assert all(t[k] == nb for k in solver)
-        assert all(v == 1 for k, v in t.items() if k not in solver)
+        for sg in (0, 1, 2):
+            t = felbm.Context(19, solver_batch=nb, lds_staging=sg).tuning()
+            assert all(t[k] == (nb, sg) for k in solver)
+            assert all(v == (1, 1) for k, v in t.items() if k not in solver)
+
+
+def test_halo_lists():
+    """Per-tile halos of the LDS stage, brute force on a small periodic grid:
+    a 16 x 16 row-major block of a 32 x 32 grid in caller order has as halo
+    the 32-node rows above and below plus the wrap-around columns."""
+    ctx = felbm.Context(9, node_order=0)
+    ctx.upload_mesh(0, grid_mesh_2d(32, 32, jitter=0.0))
+    info = ctx.layout_info()
+    # tile = grid rows 8k .. 8k + 7 (256 nodes); neighbours of the P1 split
+    # with diagonal (0,0)-(1,1) reach one grid row up and down: 2 x 32
+    assert info["halo_max"] == 64 and info["halo_mean"] == 64.0
+    z = felbm.Context(9, node_order=1)
+    z.upload_mesh(0, grid_mesh_2d(32, 32, jitter=0.0))
+    zi = z.layout_info()
+    # Z-order tiles are 16 x 16 blocks: 4 sides of 16 plus 2 corners
+    assert zi["halo_max"] == 66 and zi["halo_mean"] == 66.0
 
 
 def test_inverted_element_rejected():

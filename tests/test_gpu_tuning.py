@@ -1,10 +1,11 @@
-"""Population batch of the mass-solve pipelines.
+"""Schedule of the mass solve: population batch and LDS staging.
 
-The batch only sets how far ahead a solver kernel issues its loads; every
-population's row sum and its tile reduction run in the same order, so every
-setting (and the per-kernel choice the library times on the first step)
-must give bitwise equal states, and one of them is checked against the
-oracle.
+The batch only sets how far ahead a solver kernel issues its loads (or how
+many populations an LDS pass stages); every population's row sum and its
+tile reduction run in the same order, so all batches of one form give
+bitwise equal states.  The staged form reads the same neighbour values from
+LDS instead of memory; it agrees with the direct form to rounding (the two
+may contract multiply-adds differently) and is checked against the oracle.
 """
 import numpy as np
 import pytest
@@ -35,43 +36,52 @@ def _workload(dim):
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("mass_mode", [0, 2])
-def test_solver_batch_bitwise_equal(felbm, oracle_mod, dim, precision, mass_mode):
+@pytest.mark.parametrize("node_order", [0, 1])
+def test_solver_schedules(felbm, oracle_mod, dim, precision, mass_mode, node_order):
     w = _workload(dim)
     steps = 6
+    inst = w.instances[0]
+    o = oracle_mod.Oracle(inst.mesh, w.lattice, inst.phys)
+    o.init(inst.rho0, inst.u0, inst.p0)
+    o.step(steps)
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    used = ("cheb",) if mass_mode == 2 else ("cg_init", "cg_a", "cg_b")
     states = {}
-    for nb in (1, 2, 4, 0):
-        print("case", dim, precision, mass_mode, nb, flush=True)
-        ctx = felbm.from_workload(w, precision=precision, mass_mode=mass_mode, solver_batch=nb)
-        ctx.step(steps)
-        ctx.sync()
-        states[nb] = ctx.get_state(0)
-        t = ctx.tuning()
-        used = ("cheb",) if mass_mode == 2 else ("cg_init", "cg_a", "cg_b")
-        for name in SOLVER:
-            if nb:
-                assert t[name] == nb
-            else:
-                assert t[name] in ((1, 2, 4) if name in used else (1,)), (name, t[name])
-        assert all(v == 1 for k, v in t.items() if k not in SOLVER)
-        if nb == 4:
-            inst = w.instances[0]
-            o = oracle_mod.Oracle(inst.mesh, w.lattice, inst.phys)
-            o.init(inst.rho0, inst.u0, inst.p0)
-            o.step(steps)
+    for sg in (1, 2):
+        for nb in (1, 2, 4):
+            print("case", dim, precision, mass_mode, node_order, sg, nb, flush=True)
+            ctx = felbm.from_workload(w, precision=precision, mass_mode=mass_mode, solver_batch=nb,
+                                      lds_staging=sg, node_order=node_order)
+            ctx.step(steps)
+            ctx.sync()
+            states[sg, nb] = ctx.get_state(0)
+            t = ctx.tuning()
+            assert all(t[name] == (nb, sg) for name in SOLVER)
             e = compare_fields(ctx.read_fields(0), o.fields(), inst)
-            tol = 1e-11 if precision == "fp64" else 2e-5
             for k in ("rho", "u", "C"):
-                assert e[k] < tol, (k, e[k])
-    for nb in (2, 4, 0):
-        np.testing.assert_array_equal(states[1], states[nb])
+                assert e[k] < tol, (sg, nb, k, e[k])
+        for nb in (2, 4):
+            np.testing.assert_array_equal(states[sg, 1], states[sg, nb])
+    # the tuner's choice is one of the candidates, for the kernels in use
+    ctx = felbm.from_workload(w, precision=precision, mass_mode=mass_mode, node_order=node_order)
+    ctx.step(steps)
+    ctx.sync()
+    t = ctx.tuning()
+    for name in SOLVER:
+        b, sg = t[name]
+        assert (b in (1, 2, 4) and sg in (1, 2)) if name in used else (b, sg) == (1, 1), (name, t[name])
+    e = compare_fields(ctx.read_fields(0), o.fields(), inst)
+    for k in ("rho", "u", "C"):
+        assert e[k] < tol, ("tuned", k, e[k])
 
 
 def test_tuning_reads_zero_before_first_step(felbm):
     w = _workload(2)
     ctx = felbm.from_workload(w, precision="fp32")
     t = ctx.tuning()
-    assert all(t[k] == 0 for k in SOLVER)
+    assert all(t[k] == (0, 0) for k in SOLVER)
     ctx.step(1)
     ctx.sync()
     t = ctx.tuning()
-    assert t["cheb"] == 1 and all(t[k] in (1, 2, 4) for k in ("cg_init", "cg_a", "cg_b"))
+    assert t["cheb"] == (1, 1)
+    assert all(t[k][0] in (1, 2, 4) and t[k][1] in (1, 2) for k in ("cg_init", "cg_a", "cg_b"))
