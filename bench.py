@@ -71,11 +71,13 @@ def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, 
     return 0.0
 
 
-def cpu_baseline(workload, target_s: float = 15.0):
-    """The FP64 oracle, as it stands, on the same workload for ~target_s of CPU time."""
+def cpu_baseline(workload, target_s: float = 15.0, mass_mode: int = 0):
+    """The FP64 oracle, as it stands, on the same workload for ~target_s of
+    CPU time (lumped mass when the device runs lumped, else its exact
+    consistent-mass solve)."""
     from oracle import oracle as O
     inst = workload.instances[0]
-    o = O.Oracle(inst.mesh, workload.lattice, inst.phys)
+    o = O.Oracle(inst.mesh, workload.lattice, inst.phys, mass_mode=1 if mass_mode == 1 else 0)
     o.init(inst.rho0, inst.u0, inst.p0)
     t0 = time.perf_counter()
     o.step(1)
@@ -91,21 +93,20 @@ def cpu_baseline(workload, target_s: float = 15.0):
     return out, o, steps
 
 
-def measured_traffic(workload: str, precision: str, mass_mode: int, kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by their copy-kernel
-    calibration), or None when no summary covers this configuration or the
-    kernel source changed since the counters were taken."""
-    import hashlib
+def measured_traffic(workload: str, precision: str, mass_mode: int, kernel: str, name: str | None):
+    """HBM bytes per launch of kernel `name` (class `kernel`) from the
+    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by
+    their copy-kernel calibration), or None when no summary covers this
+    configuration and kernel or the device sources changed since the
+    counters were taken."""
+    from paper_1608_01906_amd.profiling import device_source_hash, lookup_traffic
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic_{precision}_mass{mass_mode}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1608_01906_amd", "csrc", "felbm_kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["kernel_source_sha256_16"]:
+    if device_source_hash() != rec["kernel_source_sha256_16"]:
         return None
-    k = rec["kernels"].get(kernel)
-    return k["traffic_bytes"] if k else None
+    return lookup_traffic(rec, kernel, name)
 
 
 def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="channel2d"):
@@ -156,18 +157,25 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="chan
                           bytes_per_launch=int(b), gbs=round(b / (avg_ms * 1e-3) / 1e9, 1))
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     dk = kern[dom]
+    sched = ctx.tuning()
+    dom_name = None
+    if dom in ("cg_init", "cg_a", "cg_b", "cheb"):
+        from paper_1608_01906_amd.profiling import solver_kernel_name
+        b, sg = sched[dom]
+        dom_name = solver_kernel_name(dom, precision, info["ell_width"], 2 * (w.lattice - 1), b, sg == 2)
     step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in kern.values()) / prof_steps
     res = dict(value=N * P * steps / secs, ms_per_step=secs / steps * 1e3, cg_iters=info["cg_iters"],
                status=status,
                roofline=dict(bound="hbm", kernel=dom, achieved=dk["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                              frac=round(dk["gbs"] / HBM_PEAK_GBS, 4),
-                             traffic=measured_traffic(workload, precision, mass_mode, dom),
-                             bytes_per_launch=dk["bytes_per_launch"], avg_launch_us=dk["avg_us"]),
+                             traffic=measured_traffic(workload, precision, mass_mode, dom, dom_name),
+                             bytes_per_launch=dk["bytes_per_launch"], avg_launch_us=dk["avg_us"],
+                             kernel_instance=dom_name),
                step_algorithmic_gbs=round(step_bytes / (secs / steps) / 1e9, 1),
                step_frac=round(step_bytes / (secs / steps) / 1e9 / HBM_PEAK_GBS, 4),
                kernels=kern,
                schedule={k: dict(batch=v[0], staging=("direct", "lds")[v[1] - 1])
-                         for k, v in ctx.tuning().items() if k in ("cg_init", "cg_a", "cg_b", "cheb") and k in kern},
+                         for k, v in sched.items() if k in ("cg_init", "cg_a", "cg_b", "cheb") and k in kern},
                halo=dict(max=info["halo_max"], mean=round(info["halo_mean"], 1)),
                event_ms_per_step=round(sum(v["total_ms"] for v in kern.values()) / prof_steps, 4))
     return res, ctx
@@ -189,6 +197,8 @@ def main():
                     help="first copy this many MiB device-to-device (HBM counter calibration)")
     ap.add_argument("--no-chebyshev", action="store_true",
                     help="skip the run with the mass matrix solved by Chebyshev iteration")
+    ap.add_argument("--mass-mode", type=int, default=0, choices=[0, 1, 2],
+                    help="mass solve of the headline run: 0 consistent (CG), 1 lumped, 2 consistent (Chebyshev)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -213,7 +223,10 @@ def main():
     inst = w.instances[0]
     N = w.n_nodes
     P = 2 * w.lattice
-    head, ctx_head = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, workload=args.workload)
+    head, ctx_head = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps,
+                             mass_mode=args.mass_mode, workload=args.workload)
+    mass = {0: f"consistent, CG x{head['cg_iters']}", 1: "lumped",
+            2: f"consistent, Chebyshev x{head['cg_iters']}"}[args.mass_mode]
     out = {
         "metric": "node-population updates/s (NPU/s)",
         "value": head["value"],
@@ -229,7 +242,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": DESCRIPTIONS.get(args.workload, w.name), "instances": len(w.instances),
                    "nodes": N, "populations": P, "precision": args.precision,
-                   "mass": f"consistent, CG x{head['cg_iters']}", "dt": inst.phys.dt},
+                   "mass": mass, "dt": inst.phys.dt},
         "roofline": head["roofline"],
         "step_algorithmic_gbs": head["step_algorithmic_gbs"],
         "step_frac": head["step_frac"],
@@ -241,23 +254,24 @@ def main():
     }
     ctx64 = None
     if not args.no_fp64 and args.precision != "fp64":
-        r64, ctx64 = run_gpu(w, "fp64", args.steps, args.warmup, args.profile_steps, workload=args.workload)
+        r64, ctx64 = run_gpu(w, "fp64", args.steps, args.warmup, args.profile_steps, mass_mode=args.mass_mode,
+                             workload=args.workload)
         out["fp64_plain"] = {k: r64[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
                                                  "step_frac", "event_ms_per_step")}
         out["speedup_vs_fp64_plain"] = head["value"] / r64["value"]
-    if not args.no_chebyshev:
+    if not args.no_chebyshev and args.mass_mode != 2:
         rch, _ = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, mass_mode=2,
                          workload=args.workload)
         out["chebyshev_solve"] = {k: rch[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
                                                       "step_frac", "event_ms_per_step", "schedule")}
     if not args.no_cpu_baseline:
         from paper_1608_01906_amd import felbm
-        cb, orc, s_steps = cpu_baseline(w)
+        cb, orc, s_steps = cpu_baseline(w, mass_mode=args.mass_mode)
         out["cpu_baseline"] = cb
         ref = orc.fields()
         errs = {}
         for prec in [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"]):
-            c = felbm.from_workload(w, precision=prec, device="cuda:0")
+            c = felbm.from_workload(w, precision=prec, device="cuda:0", mass_mode=args.mass_mode)
             c.step(s_steps)
             c.sync(allow_notconv=True)
             errs[prec] = {k: float(f"{v:.3e}") for k, v in compare_fields(c.read_fields(0), ref, inst).items()}
