@@ -32,6 +32,8 @@ DESCRIPTIONS = {
     "rt2d": "rt2d: Rayleigh-Taylor, 1024x4096 jittered P1 mesh between walls, D2Q9, Atwood 0.5",
     "droplet3d": "droplet3d: static drop, 128^3 periodic jittered Kuhn-tet mesh, D3Q19, density ratio 100",
     "ensemble2d": "ensemble2d: 64 independent periodic drops, sides 32..512, density ratios 1..1000, D2Q9",
+    "translate2d": "translate2d: drop carried by u0 = 0.02 through a 128x128 periodic jittered P1 mesh, D2Q9, "
+                   "density ratio 100",
 }
 
 

@@ -5,4 +5,5 @@ method's arithmetic.
 """
 from .mesh import grid_mesh_2d, grid_mesh_3d, splitmix64, uniform01, mesh_summary  # noqa: F401
 from .workloads import (Phys, Instance, Workload, WORKLOADS, droplet2d, droplet3d,  # noqa: F401
-                        channel2d, rt2d, ensemble2d, droplet_instance, channel_profile, DT_RUN)
+                        channel2d, rt2d, ensemble2d, translate2d, droplet_instance, channel_profile,
+                        DT_RUN)
