@@ -108,6 +108,13 @@ typedef struct {
                              Every schedule computes the same sums in the same order; results agree
                              to rounding (the staged and direct forms may contract multiply-adds
                              differently) */
+    int fused_reductions; /* consistent-mass CG: 1 = a finalize launch forms each CG scalar from the
+                             tile partials (two per iteration); 2 = fused: 1024-thread blocks leave
+                             at most 256 partials per instance and every block of the next launch
+                             sums them itself (D2Q9 layouts with instances of at most 1024 tiles,
+                             else fel_bind returns FEL_EINVAL); 0 = chosen by timing both solves on
+                             the bound layout before the first step (1 where fused is unavailable).
+                             Same results to rounding (the partial sums group rows differently) */
 } fel_options;
 
 /* Physical parameters of one instance (Section 2.1).  rho_l is the heavy
@@ -210,10 +217,12 @@ FEL_API fel_status fel_layout_info(fel_ctx* ctx, int64_t* rows, int* ell_width, 
 
 /* Schedule in use for each kernel class k < max_classes (same classes and
  * order as fel_profile_read): population batch and staging (1 direct,
- * 2 LDS-staged); kernels without a tunable schedule read 1.  Values left to
- * the tuner (option 0) read 0 until the first fel_step.  batch and staging
- * may be NULL. */
-FEL_API fel_status fel_tuning(fel_ctx* ctx, int max_classes, int* n_classes, int* batch, int* staging);
+ * 2 LDS-staged); kernels without a tunable schedule read 1; and the CG
+ * reduction form (fused_reductions: 1 or 2).  Values left to the tuner
+ * (option 0) read 0 until the first fel_step.  batch, staging and fused may
+ * be NULL. */
+FEL_API fel_status fel_tuning(fel_ctx* ctx, int max_classes, int* n_classes, int* batch, int* staging,
+                              int* fused);
 
 FEL_API fel_status fel_destroy(fel_ctx* ctx);
 FEL_API const char* fel_last_error(const fel_ctx* ctx);

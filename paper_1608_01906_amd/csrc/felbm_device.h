@@ -119,7 +119,7 @@ template <typename T> __device__ __forceinline__ void st(void* p, int64_t i, T v
 // kernel needs a device-scope fence (on multi-XCD parts such a fence writes
 // back and invalidates the XCD's L2, which would discard the neighbour
 // reuse the gathers depend on).
-template <int NP>
+template <int NP, int NW = TILE / 64>
 struct TileReducer {
     static_assert(NP <= TILE, "too many reduction values");
     double (*lds)[NP];
@@ -139,11 +139,20 @@ struct TileReducer {
     // the tile's partials, population-major: partial[j][tile]
     __device__ __forceinline__ void finish(const DevLayout& L, int tile) {
         __syncthreads();
-        for (int j = threadIdx.x; j < NP; j += TILE) {
+        for (int j = threadIdx.x; j < NP; j += NW * 64) {
             double s = 0.0;
 #pragma unroll
-            for (int w = 0; w < TILE / 64; w++) s += lds[w][j];
+            for (int w = 0; w < NW; w++) s += lds[w][j];
             L.partial[(int64_t)j * L.ntiles + tile] = s;
+        }
+    }
+    // the block's partials over its first nw waves: dst[j * stride + index]
+    __device__ __forceinline__ void finish_to(double* dst, int stride, int index, int nw) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < NP; j += NW * 64) {
+            double s = 0.0;
+            for (int w = 0; w < nw; w++) s += lds[w][j];
+            dst[(int64_t)j * stride + index] = s;
         }
     }
 };
@@ -151,6 +160,10 @@ struct TileReducer {
 #define FEL_REDUCER(NAME, NP)                         \
     __shared__ double NAME##_buf[TILE / 64][NP];      \
     TileReducer<NP> NAME(NAME##_buf)
+
+#define FEL_REDUCER_N(NAME, NP, NW)                   \
+    __shared__ double NAME##_buf[NW][NP];             \
+    TileReducer<NP, NW> NAME(NAME##_buf)
 
 // gathers through a uniform base and a 32-bit byte offset
 template <typename T>

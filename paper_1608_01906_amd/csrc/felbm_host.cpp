@@ -103,7 +103,7 @@ struct fel_ctx {
     int hmax = 0, sw = 0;
     int64_t halo_total = 0;
     struct Off {
-        size_t lcol, halo_ptr, halo_col, col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, rho, grad,
+        size_t lcol, halo_ptr, halo_col, fblocks, fpart0, fpart1, srz, col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, rho, grad,
             mu, S, u, p, partial, counter, rz, rz0, alpha, beta, sums, status, end;
     } off{};
     // graph
@@ -114,6 +114,13 @@ struct fel_ctx {
     // LDS staging (1 direct gathers, 2 staged); 0 = not yet tuned
     int batch[KC_COUNT] = {};
     int stage[KC_COUNT] = {};
+    // fused-reduction CG: 0 = not yet chosen, 1 = finalize launches, 2 = fused
+    // (fbatch: the fused kernels' population batches); fblocks in dispatch order
+    int fused = 0;
+    int fbatch[KC_COUNT] = {};
+    bool fused_ok = false;
+    std::vector<int32_t> fblocks;  // 4 ints per block
+    int nfb = 0;
     // profiling
     bool profiling = false;
     std::vector<ProfEvent> pending;
@@ -294,6 +301,7 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
     const int nb = opt->solver_batch;
     if (nb != 0 && nb != 1 && nb != 2 && nb != 4) return FEL_EINVAL;
     if (opt->lds_staging < 0 || opt->lds_staging > 2) return FEL_EINVAL;
+    if (opt->fused_reductions < 0 || opt->fused_reductions > 2) return FEL_EINVAL;
     fel_ctx* c = new (std::nothrow) fel_ctx();
     if (!c) return FEL_ENOMEM;
     c->opt = *opt;
@@ -311,6 +319,7 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
         c->batch[k] = nb;
         c->stage[k] = opt->lds_staging;
     }
+    c->fused = opt->fused_reductions;
     *out = c;
     return FEL_OK;
 }
@@ -525,6 +534,40 @@ static void build_halos(fel_ctx* c) {
     c->sw = (TILE + c->hmax + 31) / 32 * 32;
 }
 
+// Blocks of the fused-reduction CG: each instance's tiles in groups of
+// kFusedTiles (the last group may be short), listed in dispatch order so
+// that, with block b running on XCD b % 8, each XCD receives a contiguous
+// range of blocks (as tile_of_block does for the one-tile blocks).  The
+// path is available for D2Q9 layouts whose instances have at most
+// kFusedMaxBlocks blocks.
+static void build_fused_blocks(fel_ctx* c) {
+    std::vector<int32_t> order;
+    c->fused_ok = c->opt.lattice == 9 && (c->W == 7 || c->W == 12);
+    for (int i = 0; i < c->ninst; i++) {
+        InstParams& P = c->inst[i].P;
+        const int nb = (P.tile_count + kFusedTiles - 1) / kFusedTiles;
+        P.fb_begin = (int)(order.size() / 4);
+        P.fb_count = nb;
+        c->fused_ok = c->fused_ok && nb <= kFusedMaxBlocks;
+        for (int k = 0; k < nb; k++) {
+            order.push_back(P.tile_begin + k * kFusedTiles);
+            order.push_back(std::min(kFusedTiles, P.tile_count - k * kFusedTiles));
+            order.push_back(i);
+            order.push_back(k);
+        }
+    }
+    const int nb = (int)(order.size() / 4);
+    c->nfb = nb;
+    c->fblocks.assign(order.size(), 0);
+    constexpr int NX = 8;
+    const int base = nb / NX, extra = nb % NX;
+    for (int b = 0; b < nb; b++) {
+        const int xcd = b % NX, idx = b / NX;
+        const int src = xcd * base + std::min(xcd, extra) + idx;
+        for (int q = 0; q < 4; q++) c->fblocks[4 * b + q] = order[4 * src + q];
+    }
+}
+
 static fel_status plan_layout(fel_ctx* c) {
     int n = 0;
     while (n < (int)c->inst.size() && c->inst[n].mesh.present) n++;
@@ -553,6 +596,7 @@ static fel_status plan_layout(fel_ctx* c) {
     c->R = rows;
     c->ntiles = (int)(rows / TILE);
     build_halos(c);
+    build_fused_blocks(c);
     const size_t R = (size_t)rows;
     const int W = c->W, NB = c->NB, NP = c->NP, Q = c->opt.lattice, D = c->lat.D;
     const size_t s = elem_size(c->opt.precision);
@@ -594,6 +638,10 @@ static fel_status plan_layout(fel_ctx* c) {
     f.alpha = take(8 * (size_t)n * NP);
     f.beta = take(8 * (size_t)n * NP);
     f.sums = take(8 * 8 * (size_t)n);
+    f.fblocks = take(16 * (size_t)std::max(c->nfb, 1));
+    f.fpart0 = take(8 * (size_t)NP * std::max(c->nfb, 1));
+    f.fpart1 = take(8 * (size_t)NP * std::max(c->nfb, 1));
+    f.srz = take(8 * 2 * (size_t)n * NP);
     f.status = take(4);
     f.end = o;
     c->ws_bytes = o;
@@ -660,6 +708,7 @@ static fel_status upload_operators(fel_ctx* c) {
     HIP_TRY(c, put(c->off.mlump, mlump.data(), R * 8));
     HIP_TRY(c, put(c->off.wmask, wmask.data(), R * 4));
     HIP_TRY(c, put(c->off.tile_inst, c->tile_inst.data(), c->tile_inst.size() * 4));
+    if (c->nfb) HIP_TRY(c, put(c->off.fblocks, c->fblocks.data(), c->fblocks.size() * 4));
     HIP_TRY(c, hipMemsetAsync(c->dev + c->off.counter, 0, 4 * c->ninst, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->dev + c->off.status, 0, 4, c->stream));
     // padding rows of every vector start at zero
@@ -713,6 +762,11 @@ static void set_pointers(fel_ctx* c) {
     L.beta = reinterpret_cast<double*>(d + f.beta);
     L.sums = reinterpret_cast<double*>(d + f.sums);
     L.status = reinterpret_cast<uint32_t*>(d + f.status);
+    L.fblocks = reinterpret_cast<const int4*>(d + f.fblocks);
+    L.nfb = c->nfb;
+    L.fpart0 = reinterpret_cast<double*>(d + f.fpart0);
+    L.fpart1 = reinterpret_cast<double*>(d + f.fpart1);
+    L.srz = reinterpret_cast<double*>(d + f.srz);
     L.cg_tol2 = c->cg_tol * c->cg_tol;
     L.lap_mode = c->opt.laplacian_mode;
 }
@@ -727,6 +781,9 @@ fel_status fel_bind(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
         return fail(c, FEL_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, c->ws_bytes);
     c->dev = static_cast<char*>(dev_ptr);
     c->stream = static_cast<hipStream_t>(hip_stream);
+    if (c->fused == 2 && !c->fused_ok)
+        return fail(c, FEL_EINVAL, "fused reductions need a D2Q9 layout (ELL width 7 or 12) with at most %d "
+                    "blocks of %d tiles per instance", kFusedMaxBlocks, kFusedTiles);
     set_pointers(c);
     st = upload_operators(c);
     if (st != FEL_OK) return st;
@@ -808,6 +865,20 @@ hipError_t enqueue_solve(fel_ctx* c) {
             cur = 1 - cur;
         }
         return hipSuccess;
+    }
+    if (c->fused == 2) {
+        if ((e = timed(c, KC_CG_INIT, [&] { return launch_cg_init_fused(L, c->fbatch[KC_CG_INIT], s); })) !=
+            hipSuccess)
+            return e;
+        for (int it = 0; it < c->cg_iters; it++) {
+            if ((e = timed(c, KC_CG_A, [&] { return launch_cg_a_fused(L, it, c->fbatch[KC_CG_A], s); })) !=
+                hipSuccess)
+                return e;
+            if ((e = timed(c, KC_CG_B, [&] { return launch_cg_b_fused(L, it, c->fbatch[KC_CG_B], s); })) !=
+                hipSuccess)
+                return e;
+        }
+        return timed(c, KC_FINALIZE, [&] { return launch_fused_check(L, s); });
     }
     const int ni = c->ninst, np = c->NP;
     auto fin = [&](int op) { return timed(c, KC_FINALIZE, [&] { return launch_finalize(L, 0, ni, op, np, s); }); };
@@ -901,6 +972,108 @@ fel_status tune_schedule(fel_ctx* c) {
     c->event_pool.push_back(a);
     c->event_pool.push_back(b);
     return st;
+}
+
+// Times one launch kind with HIP events: kWarm untimed then kReps timed.
+template <typename F>
+hipError_t time_launches(fel_ctx* c, hipEvent_t a, hipEvent_t b, F&& run, float* ms) {
+    constexpr int kWarm = 2, kReps = 8;
+    (void)hipGetLastError();
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < kWarm && e == hipSuccess; r++) e = run();
+    if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+    for (int r = 0; r < kReps && e == hipSuccess; r++) e = run();
+    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    return e;
+}
+
+// Population batches of the fused kernels (1, 2, 4; width 12 only 1), by
+// timing, unless solver_batch fixes them.
+fel_status tune_fused_batches(fel_ctx* c) {
+    const DevLayout& L = c->L;
+    hipStream_t s = c->stream;
+    if (c->opt.solver_batch) {
+        for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B}) c->fbatch[cls] = c->W == 7 ? c->opt.solver_batch : 1;
+        return FEL_OK;
+    }
+    hipEvent_t a = get_event(c), b = get_event(c);
+    if (!a || !b) return fail(c, FEL_EDEVICE, "event creation failed");
+    fel_status st = FEL_OK;
+    for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B}) {
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int t : {1, 2, 4}) {
+            if (c->W != 7 && t != 1) continue;
+            float ms = 0.0f;
+            hipError_t e = time_launches(c, a, b, [&] {
+                return cls == KC_CG_INIT ? launch_cg_init_fused(L, t, s)
+                       : cls == KC_CG_A  ? launch_cg_a_fused(L, 1, t, s)
+                                         : launch_cg_b_fused(L, 1, t, s);
+            }, &ms);
+            if (e != hipSuccess) {
+                st = fail(c, FEL_EDEVICE, "fused tuning launch failed: %s", hipGetErrorString(e));
+                break;
+            }
+            if (best == 0 || ms < best_ms) best = t, best_ms = ms;
+        }
+        if (st != FEL_OK) break;
+        c->fbatch[cls] = best;
+    }
+    c->event_pool.push_back(a);
+    c->event_pool.push_back(b);
+    return st;
+}
+
+// Chooses between the finalize-launch and the fused-reduction CG when the
+// option left it open: graphs of the whole mass solve are built both ways
+// and timed, and the faster is kept (without graphs, fused: fewer launches
+// is then the whole gain).  Like the other tuning it touches only the
+// solve's scratch; the status word, which the final residual check may set
+// on that scratch, is restored afterwards.
+fel_status choose_fused(fel_ctx* c) {
+    if (!c->use_graph) {
+        c->fused = 2;
+        return FEL_OK;
+    }
+    hipStream_t s = c->stream;
+    uint32_t saved = 0;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipMemcpy(&saved, c->dev + c->off.status, 4, hipMemcpyDeviceToHost));
+    hipEvent_t a = get_event(c), b = get_event(c);
+    if (!a || !b) return fail(c, FEL_EDEVICE, "event creation failed");
+    fel_status st = FEL_OK;
+    int best = 1;
+    float best_ms = 0.0f;
+    for (int mode : {1, 2}) {
+        c->fused = mode;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            e = enqueue_solve(c);
+            hipError_t e2 = hipStreamEndCapture(s, &g);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = time_launches(c, a, b, [&] { return hipGraphLaunch(ge, s); }, &ms);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            st = fail(c, FEL_EDEVICE, "solve timing failed: %s", hipGetErrorString(e));
+            break;
+        }
+        if (mode == 1 || ms < best_ms) best = mode, best_ms = ms;
+    }
+    c->fused = st == FEL_OK ? best : 1;
+    c->event_pool.push_back(a);
+    c->event_pool.push_back(b);
+    if (st != FEL_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipMemcpy(c->dev + c->off.status, &saved, 4, hipMemcpyHostToDevice));
+    return FEL_OK;
 }
 
 hipError_t enqueue_step(fel_ctx* c) {
@@ -1013,6 +1186,15 @@ fel_status fel_step(fel_ctx* c, int n_steps) {
     if (untuned) {
         fel_status st = tune_schedule(c);
         if (st != FEL_OK) return st;
+    }
+    if (c->fused != 1 && !c->fbatch[KC_CG_A]) {
+        if (!c->fused_ok || c->opt.mass_mode != FEL_MASS_CONSISTENT) {
+            c->fused = 1;  // the fused path needs a 2-D layout, small instances and the CG solve
+        } else {
+            fel_status st = tune_fused_batches(c);
+            if (st == FEL_OK && c->fused == 0) st = choose_fused(c);
+            if (st != FEL_OK) return st;
+        }
     }
     if (c->profiling || !c->use_graph) {
         // profiling launches directly: each kernel's events are stamped by its own dispatch
@@ -1293,12 +1475,15 @@ fel_status fel_layout_info(fel_ctx* c, int64_t* rows, int* ell_width, int* pops,
     return FEL_OK;
 }
 
-fel_status fel_tuning(fel_ctx* c, int max_classes, int* n_classes, int* batch, int* staging) {
+fel_status fel_tuning(fel_ctx* c, int max_classes, int* n_classes, int* batch, int* staging, int* fused) {
     if (!c || !n_classes) return FEL_EINVAL;
     *n_classes = KC_COUNT;
+    const bool f = c->fused == 2;
+    if (fused) *fused = c->fused;
     for (int k = 0; k < KC_COUNT && k < max_classes; k++) {
-        if (batch) batch[k] = c->batch[k];
-        if (staging) staging[k] = c->stage[k];
+        const bool fk = f && (k == KC_CG_INIT || k == KC_CG_A || k == KC_CG_B);
+        if (batch) batch[k] = fk ? c->fbatch[k] : c->batch[k];
+        if (staging) staging[k] = fk ? 1 : c->stage[k];
     }
     return FEL_OK;
 }

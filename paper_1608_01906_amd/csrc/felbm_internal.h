@@ -21,6 +21,7 @@ struct InstParams {
     double scale;          // deviation scale s (FP32 modes): psi_a = w_a (ref + s d_a)
     int row_begin, row_end;  // valid rows of the instance [row_begin, row_end)
     int tile_begin, tile_count;
+    int fb_begin, fb_count;  // fused-reduction blocks of the instance (see fblocks)
 };
 
 // Device pointers of one context (all sub-allocated in the bound workspace).
@@ -71,6 +72,15 @@ struct DevLayout {
     double* beta;          // [ninst][2(Q-1)]
     double* sums;          // [ninst][8]
     uint32_t* status;      // [1] bit 0 non-finite, bit 1 CG residual above tolerance
+    // fused reductions (2-D): blocks of up to 4 tiles; entry b of fblocks =
+    // (first tile, tiles, instance, block index within the instance), in
+    // dispatch order; block partials [NP][nfb] alternate between fpart0
+    // (r.z) and fpart1 (p.q); srz [2][ninst][NP] holds r.z by iteration parity
+    const int4* fblocks;
+    int nfb;
+    double* fpart0;
+    double* fpart1;
+    double* srz;
     double cg_tol2;        // squared relative residual tolerance of the CG check
     int lap_mode;          // 0 nested recovery, 1 weak form
 };
@@ -114,6 +124,14 @@ hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool flip
 // nvals values per tile (partials stored population-major)
 hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int nvals, hipStream_t s);
 hipError_t launch_lumped(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+// Fused-reduction CG (2-D, no finalize launches): every block sums the
+// previous launch's block partials of its instance itself.  it = iteration.
+hipError_t launch_cg_init_fused(const DevLayout& L, int batch, hipStream_t s);
+hipError_t launch_cg_a_fused(const DevLayout& L, int it, int batch, hipStream_t s);
+hipError_t launch_cg_b_fused(const DevLayout& L, int it, int batch, hipStream_t s);
+hipError_t launch_fused_check(const DevLayout& L, hipStream_t s);
+constexpr int kFusedTiles = 4;       // tiles per fused-reduction block
+constexpr int kFusedMaxBlocks = 256; // per instance (one round of loads per lane in the prologue)
 // Chebyshev solve: first launch writes x_0 to buffer out0 and x_1 to the
 // other (0 = X, 1 = Pa); each later launch reads x_k from buffer cur.
 hipError_t launch_cheb_first(const DevLayout& L, int tile_begin, int ntiles, int out0, double gamma, int batch,

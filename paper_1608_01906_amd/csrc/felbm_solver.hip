@@ -85,12 +85,19 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(DevLayout L, int inst_
 // The FP64 dot products are reduced RG populations at a time.
 constexpr int RG = 4;
 
-template <int NP, int CH, class Body>
-__device__ __forceinline__ void run_rows(Body& body, TileReducer<NP>* red) {
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+// `after_first` runs once the first batch's loads are issued (the fused
+// kernels form their CG scalars there, so that latency overlaps the loads).
+template <int NP, int CH, class Body, class Red, class Hook = NoHook>
+__device__ __forceinline__ void run_rows(Body& body, Red* red, Hook after_first = Hook()) {
     static_assert(NP % CH == 0 && NP % RG == 0, "population batches must tile NP");
     typename Body::Regs buf[2][CH];
 #pragma unroll
     for (int u = 0; u < CH; u++) body.load(u, buf[0][u]);
+    after_first();
     double dots[RG];
 #pragma unroll
     for (int j0 = 0; j0 < NP; j0 += CH) {
@@ -145,6 +152,7 @@ struct CgInitRows {
     T *X, *Rv;
     int64_t R;
     int row;
+    bool live = true;  // false: a fused block's spare wave (loads only, no stores, zero terms)
     __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* b = rhs + (int64_t)j * R;
 #pragma unroll
@@ -157,6 +165,7 @@ struct CgInitRows {
         for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k]);
         const T res = r.own - acc;
         const int64_t i = (int64_t)j * R + row;
+        if (!live) return 0.0;
         X[i] = r.own * o.mrow;
         Rv[i] = res;
         return (double)res * (double)res * (double)o.mrow;
@@ -175,6 +184,7 @@ struct CgARows {
     const double* beta;
     int64_t R;
     int row;
+    bool live = true;
     __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* rv = Rv + (int64_t)j * R;
 #pragma unroll
@@ -199,6 +209,7 @@ struct CgARows {
             for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k] + bet * r.h[k]);
             pown = r.own * o.mrow + bet * r.ownp;
         }
+        if (!live) return 0.0;
         Pnew[(int64_t)j * R + row] = pown;
         return (double)pown * (double)acc;
     }
@@ -215,6 +226,7 @@ struct CgBRows {
     const double* alpha;
     int64_t R;
     int row;
+    bool live = true;
     __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* p = Pn + (int64_t)j * R;
 #pragma unroll
@@ -231,6 +243,7 @@ struct CgBRows {
         const T al = (T)alpha[j];
         const int64_t i = (int64_t)j * R + row;
         const T res = r.r - al * qq;
+        if (!live) return 0.0;
         X[i] = r.x + al * r.own;
         Rv[i] = res;
         return (double)res * (double)res * (double)o.mrow;
@@ -397,6 +410,146 @@ __global__ __launch_bounds__(TILE) void k_cheb(DevLayout L, int tile_begin, int 
     b.R = R;
     b.row = row;
     run_rows<NP, CH>(b, (TileReducer<NP>*)nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Fused-reduction CG (2-D instances of up to kFusedMaxBlocks blocks).  A
+// block covers kFusedTiles tiles (1024 threads), so an instance has at most
+// 256 block partials, and instead of a finalize launch between the two
+// kernels of an iteration every block sums the partials the previous launch
+// left for its instance (wave w sums values w, w + 16, ...: a few coalesced
+// loads per lane), in the same fixed order in every block, so all blocks of
+// an instance hold bitwise the same alpha or beta.  r.z is kept by
+// iteration parity in srz (the first block of the instance writes it; the
+// launch reads the other slot), so no block reads what this launch writes.
+// Block partials: cg_init and cg_b write fpart0 (r.z), cg_a writes fpart1
+// (p.q).  One check launch after the last iteration replaces the final
+// residual check of the finalize path.
+constexpr int FB_THREADS = kFusedTiles * TILE;
+constexpr int FB_WAVES = FB_THREADS / 64;
+
+#define FEL_FUSED_LAYOUT()                                            \
+    const int4 fb = L.fblocks[blockIdx.x];                            \
+    const int64_t R = L.R;                                            \
+    const int sub = threadIdx.x / TILE;                               \
+    const bool active = sub < fb.y;                                   \
+    const int tile = fb.x + (active ? sub : 0);                       \
+    const int row = tile * TILE + (threadIdx.x & (TILE - 1));         \
+    const int inst = fb.z;                                            \
+    const int pidx = L.params[inst].fb_begin + fb.w
+
+// tot[j] = sum over the instance's blocks of src[j][block], j < NP
+template <int NP>
+__device__ __forceinline__ void fused_totals(const DevLayout& L, const double* src, int inst, double* tot) {
+    const InstParams& P = L.params[inst];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < NP; j += FB_WAVES) {
+        const double* p = src + (int64_t)j * L.nfb + P.fb_begin;
+        double s = 0.0;
+        for (int b = lane; b < P.fb_count; b += 64) s += p[b];
+        s = wave_sum(s);
+        if (lane == 0) tot[j] = s;
+    }
+    __syncthreads();
+}
+
+// Every thread of a fused block runs the row pipeline (spare waves of an
+// instance's last, short block on its first tile with stores masked), so
+// all reach the same barriers.  The row operands and the first population
+// batch are loaded before the block forms its CG scalars (the hook), so the
+// two latencies overlap.
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(FB_THREADS) void k_cg_init_fused(DevLayout L) {
+    FEL_FUSED_LAYOUT();
+    FEL_REDUCER_N(red, NP, FB_WAVES);
+    CgInitRows<T, W> b;
+    b.o.load(L, R, row);
+    b.rhs = vec<T>(L.Pb);
+    b.X = vec<T>(L.X);
+    b.Rv = vec<T>(L.Rv);
+    b.R = R;
+    b.row = row;
+    b.live = active;
+    run_rows<NP, CH>(b, &red);
+    red.finish_to(L.fpart0, L.nfb, pidx, FB_WAVES);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(FB_THREADS) void k_cg_a_fused(DevLayout L, int it) {
+    FEL_FUSED_LAYOUT();
+    __shared__ double tot[NP], bet[NP];
+    const int cur = it & 1;
+    auto scalars = [&] {
+        fused_totals<NP>(L, L.fpart0, inst, tot);  // r.z of the current residual
+        if (threadIdx.x < NP) {
+            const int j = threadIdx.x;
+            if (fb.w == 0) {
+                L.srz[((int64_t)cur * L.ninst + inst) * NP + j] = tot[j];
+                if (it == 0) L.rz0[inst * NP + j] = tot[j];
+            }
+            const double old = it == 0 ? 0.0 : L.srz[((int64_t)(1 - cur) * L.ninst + inst) * NP + j];
+            bet[j] = (old != 0.0) ? tot[j] / old : 0.0;
+        }
+        __syncthreads();
+    };
+    FEL_REDUCER_N(red, NP, FB_WAVES);
+    const T* Rv = vec<T>(L.Rv);
+    const T* Pold = vec<T>(cur ? L.Pa : L.Pb);
+    T* Pnew = vec<T>(cur ? L.Pb : L.Pa);
+    if (it == 0) {
+        CgARows<T, W, true> b;
+        b.o.load(L, R, row);
+        b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.beta = bet, b.R = R, b.row = row, b.live = active;
+        run_rows<NP, CH>(b, &red, scalars);
+    } else {
+        CgARows<T, W, false> b;
+        b.o.load(L, R, row);
+        b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.beta = bet, b.R = R, b.row = row, b.live = active;
+        run_rows<NP, CH>(b, &red, scalars);
+    }
+    red.finish_to(L.fpart1, L.nfb, pidx, FB_WAVES);
+}
+
+template <typename T, int W, int NP, int CH>
+__global__ __launch_bounds__(FB_THREADS) void k_cg_b_fused(DevLayout L, int it) {
+    FEL_FUSED_LAYOUT();
+    __shared__ double tot[NP], alp[NP];
+    auto scalars = [&] {
+        fused_totals<NP>(L, L.fpart1, inst, tot);  // p.q
+        if (threadIdx.x < NP) {
+            const int j = threadIdx.x;
+            const double rz = L.srz[((int64_t)(it & 1) * L.ninst + inst) * NP + j];
+            alp[j] = (tot[j] != 0.0) ? rz / tot[j] : 0.0;
+        }
+        __syncthreads();
+    };
+    FEL_REDUCER_N(red, NP, FB_WAVES);
+    CgBRows<T, W> b;
+    b.o.load(L, R, row);
+    b.Pn = vec<T>((it & 1) ? L.Pb : L.Pa);
+    b.X = vec<T>(L.X);
+    b.Rv = vec<T>(L.Rv);
+    b.alpha = alp;
+    b.R = R;
+    b.row = row;
+    b.live = active;
+    run_rows<NP, CH>(b, &red, scalars);
+    red.finish_to(L.fpart0, L.nfb, pidx, FB_WAVES);
+}
+
+// final residual check: r.z after the last iteration against r0.z0
+template <int NP>
+__global__ __launch_bounds__(64) void k_fused_check(DevLayout L) {
+    const int inst = blockIdx.x, j = blockIdx.y;
+    const InstParams& P = L.params[inst];
+    const double* p = L.fpart0 + (int64_t)j * L.nfb + P.fb_begin;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < P.fb_count; b += 64) s += p[b];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+        const double r0 = L.rz0[inst * NP + j];
+        if (r0 > 0.0 && !(s <= L.cg_tol2 * r0)) atomicOr(L.status, 2u);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -816,6 +969,51 @@ hipError_t launch_cheb(const DevLayout& L, int tb, int nt, int cur, double omega
 }
 hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {
     return dispatch_qw<LumpedBody>(L, tb, nt, s);
+}
+
+// Fused kernels: 2-D only (the host enables the path for D2Q9 layouts).
+#define FEL_FUSED_LAUNCH(K, ch, s, ...)                                                                 \
+    do {                                                                                              \
+        if (L.Q != 9 || L.nfb <= 0) return hipErrorInvalidValue;                                     \
+        const bool f64_ = L.precision == 0;                                                           \
+        const dim3 g_(L.nfb), b_(FB_THREADS);                                                         \
+        if (L.W == 7) {                                                                               \
+            switch (ch) {                                                                             \
+            case 4: if (f64_) FEL_LAUNCH((K<double, 7, 16, 4>), g_, b_, 0, s, __VA_ARGS__);            \
+                    else FEL_LAUNCH((K<float, 7, 16, 4>), g_, b_, 0, s, __VA_ARGS__); break;          \
+            case 2: if (f64_) FEL_LAUNCH((K<double, 7, 16, 2>), g_, b_, 0, s, __VA_ARGS__);            \
+                    else FEL_LAUNCH((K<float, 7, 16, 2>), g_, b_, 0, s, __VA_ARGS__); break;          \
+            default: if (f64_) FEL_LAUNCH((K<double, 7, 16, 1>), g_, b_, 0, s, __VA_ARGS__);           \
+                     else FEL_LAUNCH((K<float, 7, 16, 1>), g_, b_, 0, s, __VA_ARGS__);                \
+            }                                                                                         \
+        } else if (L.W == 12) {                                                                       \
+            if (f64_) FEL_LAUNCH((K<double, 12, 16, 1>), g_, b_, 0, s, __VA_ARGS__);                   \
+            else FEL_LAUNCH((K<float, 12, 16, 1>), g_, b_, 0, s, __VA_ARGS__);                         \
+        } else {                                                                                      \
+            return hipErrorInvalidValue;                                                              \
+        }                                                                                             \
+    } while (0)
+
+hipError_t launch_cg_init_fused(const DevLayout& L, int batch, hipStream_t s) {
+    (void)hipGetLastError();
+    FEL_FUSED_LAUNCH(k_cg_init_fused, batch, s, L);
+    return hipGetLastError();
+}
+hipError_t launch_cg_a_fused(const DevLayout& L, int it, int batch, hipStream_t s) {
+    (void)hipGetLastError();
+    FEL_FUSED_LAUNCH(k_cg_a_fused, batch, s, L, it);
+    return hipGetLastError();
+}
+hipError_t launch_cg_b_fused(const DevLayout& L, int it, int batch, hipStream_t s) {
+    (void)hipGetLastError();
+    FEL_FUSED_LAUNCH(k_cg_b_fused, batch, s, L, it);
+    return hipGetLastError();
+}
+hipError_t launch_fused_check(const DevLayout& L, hipStream_t s) {
+    (void)hipGetLastError();
+    if (L.Q != 9 || L.nfb <= 0) return hipErrorInvalidValue;
+    FEL_LAUNCH((k_fused_check<16>), dim3(L.ninst, 16), dim3(64), 0, s, L);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int nvals, hipStream_t s) {

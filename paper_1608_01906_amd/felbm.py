@@ -30,7 +30,8 @@ ABI_SYMBOLS = ["fel_create", "fel_upload_mesh", "fel_workspace_size", "fel_bind"
 class FelOptions(C.Structure):
     _fields_ = [("lattice", C.c_int), ("precision", C.c_int), ("mass_mode", C.c_int), ("cg_iters", C.c_int),
                 ("cg_tol", C.c_double), ("laplacian_mode", C.c_int), ("max_instances", C.c_int),
-                ("node_order", C.c_int), ("solver_batch", C.c_int), ("lds_staging", C.c_int)]
+                ("node_order", C.c_int), ("solver_batch", C.c_int), ("lds_staging", C.c_int),
+                ("fused_reductions", C.c_int)]
 
 
 class FelPhys(C.Structure):
@@ -81,7 +82,8 @@ def load_library():
                                      C.POINTER(C.c_char_p)]
     lib.fel_layout_info.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                     C.POINTER(C.c_int), C.POINTER(C.c_int), _dp]
-    lib.fel_tuning.argtypes = [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.fel_tuning.argtypes = [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                               C.POINTER(C.c_int)]
     lib.fel_destroy.argtypes = [_vp]
     lib.fel_last_error.argtypes = [_vp]
     lib.fel_last_error.restype = C.c_char_p
@@ -111,10 +113,10 @@ class Context:
 
     def __init__(self, lattice: int, *, precision: str = "fp64", mass_mode: int = 0, cg_iters: int = 0,
                  cg_tol: float = 0.0, laplacian_mode: int = 0, max_instances: int = 1, node_order: int = 0,
-                 solver_batch: int = 0, lds_staging: int = 0):
+                 solver_batch: int = 0, lds_staging: int = 0, fused_reductions: int = 0):
         self.lib = load_library()
         opt = FelOptions(lattice, PREC[precision], mass_mode, cg_iters, cg_tol, laplacian_mode, max_instances,
-                         node_order, solver_batch, lds_staging)
+                         node_order, solver_batch, lds_staging, fused_reductions)
         h = _vp()
         st = self.lib.fel_create(C.byref(opt), C.byref(h))
         if st != FEL_OK:
@@ -240,12 +242,15 @@ class Context:
 
     def tuning(self):
         """Schedule in use, keyed by kernel class name: (population batch,
-        staging: 1 direct gathers, 2 LDS-staged)."""
-        n = C.c_int(0)
+        staging: 1 direct gathers, 2 LDS-staged); under "fused" the CG
+        reduction form (1 finalize launches, 2 fused)."""
+        n, fused = C.c_int(0), C.c_int(0)
         batch, staging = (C.c_int * 32)(), (C.c_int * 32)()
-        self._check(self.lib.fel_tuning(self.h, 32, C.byref(n), batch, staging), "fel_tuning")
+        self._check(self.lib.fel_tuning(self.h, 32, C.byref(n), batch, staging, C.byref(fused)), "fel_tuning")
         names = self.profile_read()
-        return {name: (batch[k], staging[k]) for k, name in enumerate(list(names)[:n.value])}
+        out = {name: (batch[k], staging[k]) for k, name in enumerate(list(names)[:n.value])}
+        out["fused"] = fused.value
+        return out
 
 
 def from_workload(workload, *, precision: str = "fp64", device: str = "cuda:0", stream=None, **opts) -> Context:

@@ -41,6 +41,8 @@ def test_bad_options_rejected():
     for sg in (3, -1):
         with pytest.raises(felbm.FelError):
             felbm.Context(9, lds_staging=sg)
+        with pytest.raises(felbm.FelError):
+            felbm.Context(9, fused_reductions=sg)
 
 
 def test_tuning_before_bind():
@@ -51,7 +53,8 @@ def test_tuning_before_bind():
         for sg in (0, 1, 2):
             t = felbm.Context(19, solver_batch=nb, lds_staging=sg).tuning()
             assert all(t[k] == (nb, sg) for k in solver)
-            assert all(v == (1, 1) for k, v in t.items() if k not in solver)
+            assert all(v == (1, 1) for k, v in t.items() if k not in solver and k != "fused")
+            assert t["fused"] == 0
 
 
 def test_halo_lists():

@@ -160,12 +160,14 @@ def test_batched_instances(felbm, oracle_mod):
 
 def test_graph_replay_deterministic(felbm):
     """Graph replay, the profiled graph and direct launches on the default
-    stream (no graph) give bitwise equal states."""
+    stream (no graph) give bitwise equal states (one fixed schedule: the
+    tuner may choose differently with and without graphs)."""
     import torch
     w = droplet2d(32, radius=8.0)
-    a = felbm.from_workload(w)
-    b = felbm.from_workload(w)
-    c = felbm.from_workload(w, stream=torch.cuda.default_stream())
+    fixed = dict(solver_batch=1, lds_staging=1, fused_reductions=1)
+    a = felbm.from_workload(w, **fixed)
+    b = felbm.from_workload(w, **fixed)
+    c = felbm.from_workload(w, stream=torch.cuda.default_stream(), **fixed)
     a.step(7)
     b.profile(True)
     b.step(7)
@@ -183,12 +185,15 @@ def test_graph_replay_deterministic(felbm):
 
 
 def test_checkpoint_restart(felbm):
+    """A state saved and restored into a fresh context continues bitwise like
+    the original (same fixed schedule in both)."""
     w = droplet2d(32, radius=8.0)
-    a = felbm.from_workload(w)
+    fixed = dict(solver_batch=1, lds_staging=1, fused_reductions=1)
+    a = felbm.from_workload(w, **fixed)
     a.step(5)
     st = a.get_state(0)
     a.step(5)
-    b = felbm.from_workload(w)
+    b = felbm.from_workload(w, **fixed)
     b.set_state(0, st)
     b.step(5)
     np.testing.assert_array_equal(a.get_state(0), b.get_state(0))

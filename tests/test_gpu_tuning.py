@@ -51,7 +51,7 @@ def test_solver_schedules(felbm, oracle_mod, dim, precision, mass_mode, node_ord
         for nb in (1, 2, 4):
             print("case", dim, precision, mass_mode, node_order, sg, nb, flush=True)
             ctx = felbm.from_workload(w, precision=precision, mass_mode=mass_mode, solver_batch=nb,
-                                      lds_staging=sg, node_order=node_order)
+                                      lds_staging=sg, node_order=node_order, fused_reductions=1)
             ctx.step(steps)
             ctx.sync()
             states[sg, nb] = ctx.get_state(0)
@@ -83,5 +83,77 @@ def test_tuning_reads_zero_before_first_step(felbm):
     ctx.step(1)
     ctx.sync()
     t = ctx.tuning()
-    assert t["cheb"] == (1, 1)
+    assert t["cheb"] == (1, 1) and t["fused"] in (1, 2)
     assert all(t[k][0] in (1, 2, 4) and t[k][1] in (1, 2) for k in ("cg_init", "cg_a", "cg_b"))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
+def test_fused_reductions_vs_oracle(felbm, oracle_mod, precision, tol):
+    """The fused-reduction CG (no finalize launches) against the oracle, on
+    one instance and on three uneven instances in one batch (one of them a
+    single partial tile); all fused batches give bitwise equal states."""
+    from paper_1608_01906_amd.inputs import Workload, droplet_instance, grid_mesh_2d
+    insts = []
+    for i, (n, ratio) in enumerate([(11, 10.0), (70, 3.0), (37, 20.0)]):
+        mesh = grid_mesh_2d(n, n, seed=700 + i)
+        insts.append(droplet_instance(mesh, radius=n / 4, rho_l=1.0, rho_v=1.0 / ratio, sigma=0.01, xi=4.0,
+                                      tau_l=0.05, tau_v=0.1, center=np.array([n / 2, n / 2])))
+    w = Workload("batch3", 9, insts, 8)
+    states = {}
+    for nb in (1, 2, 4):
+        ctx = felbm.from_workload(w, precision=precision, fused_reductions=2, solver_batch=nb)
+        ctx.step(8)
+        ctx.sync()
+        t = ctx.tuning()
+        assert t["fused"] == 2 and t["cg_a"][0] == nb, t
+        states[nb] = [ctx.get_state(i) for i in range(len(insts))]
+        if nb == 2:
+            for i, inst in enumerate(insts):
+                o = oracle_mod.Oracle(inst.mesh, 9, inst.phys)
+                o.init(inst.rho0, inst.u0, inst.p0)
+                o.step(8)
+                e = compare_fields(ctx.read_fields(i), o.fields(), inst)
+                print("fused", precision, "inst", i, e, flush=True)
+                for k in ("rho", "u", "C"):
+                    assert e[k] < tol, (i, k, e[k])
+    for nb in (2, 4):
+        for a, b in zip(states[1], states[nb]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_fused_matches_finalize_path(felbm):
+    """Fused and finalize-launch CG solve the same systems: states agree to
+    rounding after 20 steps of the 64 x 64 droplet, and the tuner's choice
+    is one of the two."""
+    w = droplet2d(64)
+    a = felbm.from_workload(w, precision="fp64", fused_reductions=1)
+    b = felbm.from_workload(w, precision="fp64", fused_reductions=2)
+    c = felbm.from_workload(w, precision="fp64")
+    for ctx in (a, b, c):
+        ctx.step(20)
+        ctx.sync()
+    assert a.tuning()["fused"] == 1 and b.tuning()["fused"] == 2 and c.tuning()["fused"] in (1, 2)
+    np.testing.assert_allclose(b.get_state(0), a.get_state(0), rtol=0, atol=1e-12)
+
+
+def test_fused_unavailable_cases(felbm):
+    """3-D layouts and instances above 1024 tiles cannot take the fused path:
+    asking for it is an error at bind, the tuner falls back to finalize
+    launches."""
+    from paper_1608_01906_amd.inputs import grid_mesh_2d, droplet_instance, Workload
+    w3 = droplet3d(11, radius=3.0, xi=3.0)
+    with pytest.raises(felbm.FelError):
+        felbm.from_workload(w3, fused_reductions=2)
+    ctx = felbm.from_workload(w3)
+    ctx.step(1)
+    ctx.sync()
+    assert ctx.tuning()["fused"] == 1
+    big = grid_mesh_2d(520, 520, seed=9)          # 270,400 nodes = 1057 tiles
+    inst = droplet_instance(big, radius=100.0, rho_l=1.0, rho_v=0.1, sigma=0.01, xi=4.0, tau_l=0.05, tau_v=0.05)
+    wb = Workload("big", 9, [inst], 1)
+    with pytest.raises(felbm.FelError):
+        felbm.from_workload(wb, precision="fp32", fused_reductions=2)
+    ctx = felbm.from_workload(wb, precision="fp32")
+    ctx.step(1)
+    ctx.sync()
+    assert ctx.tuning()["fused"] == 1
