@@ -89,15 +89,15 @@ struct NoHook {
     __device__ __forceinline__ void operator()() const {}
 };
 
-// `after_first` runs once the first batch's loads are issued (the fused
-// kernels form their CG scalars there, so that latency overlaps the loads).
+// `before_use` runs once the loads of the first two batches are issued,
+// before any population is used (the fused kernels form their CG scalars
+// there, so that latency overlaps the loads).
 template <int NP, int CH, class Body, class Red, class Hook = NoHook>
-__device__ __forceinline__ void run_rows(Body& body, Red* red, Hook after_first = Hook()) {
+__device__ __forceinline__ void run_rows(Body& body, Red* red, Hook before_use = Hook()) {
     static_assert(NP % CH == 0 && NP % RG == 0, "population batches must tile NP");
     typename Body::Regs buf[2][CH];
 #pragma unroll
     for (int u = 0; u < CH; u++) body.load(u, buf[0][u]);
-    after_first();
     double dots[RG];
 #pragma unroll
     for (int j0 = 0; j0 < NP; j0 += CH) {
@@ -106,6 +106,7 @@ __device__ __forceinline__ void run_rows(Body& body, Red* red, Hook after_first 
 #pragma unroll
             for (int u = 0; u < CH; u++) body.load(j0 + CH + u, buf[cur ^ 1][u]);
         }
+        if (j0 == 0) before_use();
 #pragma unroll
         for (int u = 0; u < CH; u++) {
             const int j = j0 + u;
