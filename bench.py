@@ -164,7 +164,8 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="chan
     if dom in ("cg_init", "cg_a", "cg_b", "cheb"):
         from paper_1608_01906_amd.profiling import solver_kernel_name
         b, sg = sched[dom]
-        dom_name = solver_kernel_name(dom, precision, info["ell_width"], 2 * (w.lattice - 1), b, sg == 2)
+        dom_name = solver_kernel_name(dom, precision, info["ell_width"], 2 * (w.lattice - 1), b, sg == 2,
+                                      sched.get("fused") == 2)
     step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in kern.values()) / prof_steps
     res = dict(value=N * P * steps / secs, ms_per_step=secs / steps * 1e3, cg_iters=info["cg_iters"],
                status=status,
@@ -176,8 +177,9 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="chan
                step_algorithmic_gbs=round(step_bytes / (secs / steps) / 1e9, 1),
                step_frac=round(step_bytes / (secs / steps) / 1e9 / HBM_PEAK_GBS, 4),
                kernels=kern,
-               schedule={k: dict(batch=v[0], staging=("direct", "lds")[v[1] - 1])
-                         for k, v in sched.items() if k in ("cg_init", "cg_a", "cg_b", "cheb") and k in kern},
+               schedule=dict({k: dict(batch=v[0], staging=("direct", "lds")[v[1] - 1])
+                              for k, v in sched.items() if k in ("cg_init", "cg_a", "cg_b", "cheb") and k in kern},
+                             reductions="fused" if sched.get("fused") == 2 else "finalize launches"),
                halo=dict(max=info["halo_max"], mean=round(info["halo_mean"], 1)),
                event_ms_per_step=round(sum(v["total_ms"] for v in kern.values()) / prof_steps, 4))
     return res, ctx

@@ -104,7 +104,7 @@ struct fel_ctx {
     int64_t halo_total = 0;
     struct Off {
         size_t lcol, halo_ptr, halo_col, fblocks, fpart0, fpart1, srz, col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, rho, grad,
-            mu, S, u, p, partial, counter, rz, rz0, alpha, beta, sums, status, end;
+            mu, S, u, p, partial, rz, rz0, alpha, beta, sums, status, end;
     } off{};
     // graph
     hipGraph_t graph = nullptr;
@@ -632,7 +632,6 @@ static fel_status plan_layout(fel_ctx* c) {
     f.u = take(s * D * R);
     f.p = take(s * R);
     f.partial = take(8 * (size_t)c->ntiles * std::max(NP, 8));
-    f.counter = take(4 * (size_t)n);
     f.rz = take(8 * (size_t)n * NP);
     f.rz0 = take(8 * (size_t)n * NP);
     f.alpha = take(8 * (size_t)n * NP);
@@ -709,7 +708,6 @@ static fel_status upload_operators(fel_ctx* c) {
     HIP_TRY(c, put(c->off.wmask, wmask.data(), R * 4));
     HIP_TRY(c, put(c->off.tile_inst, c->tile_inst.data(), c->tile_inst.size() * 4));
     if (c->nfb) HIP_TRY(c, put(c->off.fblocks, c->fblocks.data(), c->fblocks.size() * 4));
-    HIP_TRY(c, hipMemsetAsync(c->dev + c->off.counter, 0, 4 * c->ninst, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->dev + c->off.status, 0, 4, c->stream));
     // padding rows of every vector start at zero
     HIP_TRY(c, hipMemsetAsync(c->dev + c->off.psi, 0, c->off.X - c->off.psi, c->stream));
@@ -755,7 +753,6 @@ static void set_pointers(fel_ctx* c) {
     L.u = d + f.u;
     L.p = d + f.p;
     L.partial = reinterpret_cast<double*>(d + f.partial);
-    L.counter = reinterpret_cast<int32_t*>(d + f.counter);
     L.rz = reinterpret_cast<double*>(d + f.rz);
     L.rz0 = reinterpret_cast<double*>(d + f.rz0);
     L.alpha = reinterpret_cast<double*>(d + f.alpha);

@@ -65,7 +65,6 @@ struct DevLayout {
     void* p;               // [R]
     // reductions
     double* partial;       // [2(Q-1)][ntiles] tile partials (also reused for the conserved sums)
-    int32_t* counter;      // [ninst]
     double* rz;            // [ninst][2(Q-1)]
     double* rz0;           // [ninst][2(Q-1)]
     double* alpha;         // [ninst][2(Q-1)]

@@ -8,10 +8,11 @@
 // XCDs receive contiguous tile ranges, so the halo rows a tile gathers were
 // fetched by the same XCD's L2.
 //
-// Reductions (CG dot products, conserved sums) are FP64: per-tile partials
-// in a fixed order (wavefront shuffles, then LDS), then one small finalize
-// launch per instance sums the partials in a fixed order, so results are
-// bitwise reproducible.
+// This file holds the streaming right-hand side, moments, recovery,
+// collision, initialisation and conserved sums; the mass solve is in
+// felbm_solver.hip.  Reductions (conserved sums, CG dot products) are FP64:
+// per-tile partials in a fixed order (wavefront shuffles, then LDS), summed
+// per instance in a fixed order, so results are bitwise reproducible.
 #include "felbm_device.h"
 namespace fel {
 

@@ -40,13 +40,17 @@ def device_source_hash() -> str:
 
 
 def kernel_class(name: str) -> str | None:
-    """Kernel class (as in fel_profile_read) of a demangled kernel name."""
-    m = re.search(r"fel::(k_[a-z_0-9]+?)(?:_lds)?(?:<|\()", name)
+    """Kernel class (as in fel_profile_read) of a demangled kernel name:
+    LDS-staged and fused forms count as their kernel, the fused residual
+    check as a finalize."""
+    m = re.search(r"fel::(k_[a-z_0-9]+?)(?:_lds|_fused)?(?:<|\()", name)
     if not m:
         return None
     k = m.group(1)[2:]
     if k.startswith("cheb"):
         return "cheb"
+    if k == "fused_check":
+        return "finalize"
     for suffix in ("_plain", "_dev"):
         if k.endswith(suffix):
             k = k[: -len(suffix)]
@@ -76,11 +80,13 @@ def short_name(name: str) -> str:
     return re.sub(r"\(.*", "", name).replace("void ", "").strip()
 
 
-def solver_kernel_name(cls: str, precision: str, W: int, NP: int, batch: int, staged: bool) -> str:
+def solver_kernel_name(cls: str, precision: str, W: int, NP: int, batch: int, staged: bool,
+                       fused: bool = False) -> str:
     """Short name of the solver kernel a schedule launches (cheb: the
     iterate kernel, which runs all but the first of each solve)."""
     T = "double" if precision == "fp64" else "float"
-    return f"fel::k_{cls}{'_lds' if staged else ''}<{T}, {W}, {NP}, {batch}>"
+    form = "_fused" if fused and cls in ("cg_init", "cg_a", "cg_b") else ("_lds" if staged else "")
+    return f"fel::k_{cls}{form}<{T}, {W}, {NP}, {batch}>"
 
 
 def traffic(fetch_csv: str, write_csv: str, copy_mib: float, workload: str, precision: str, mass_mode: int,
