@@ -146,6 +146,53 @@ def grid_mesh_3d(nx: int, ny: int, nz: int, *, jitter: float = 0.2, seed: int = 
                 wall=np.zeros(n, np.uint8), wall_normal=np.zeros((n, 3)))
 
 
+def delaunay_mesh(dims, *, jitter: float = 0.4, seed: int = 1613) -> dict:
+    """Periodic unstructured simplex mesh (2-D triangles or 3-D tetrahedra).
+
+    Nodes: a unit grid of shape `dims` jittered by +-jitter per coordinate.
+    Elements: the Delaunay triangulation of those nodes together with their
+    3^d - 1 periodic copies, keeping the simplices whose centroid lies in the
+    base cell [0, n_x) x [0, n_y) (x [0, n_z)), a fundamental domain, so every
+    periodic simplex is kept once; a vertex taken from copy c gets the image
+    shift c.  Unlike the grid meshes the connectivity is irregular (2-D
+    valence up to about 10, 3-D up to about 22).
+    """
+    from scipy.spatial import Delaunay
+    dims = tuple(int(d) for d in dims)
+    dim = len(dims)
+    if dim not in (2, 3) or min(dims) < 3:
+        raise ValueError("need 2 or 3 axes of at least 3 nodes")
+    n = int(np.prod(dims))
+    idx = np.arange(n, dtype=np.int64)
+    coords = []
+    rem = idx
+    for d in dims[:-1]:
+        rem, r = np.divmod(rem, d)
+        coords.append(r)
+    coords.append(rem)
+    xyz = np.stack(coords, axis=1).astype(np.float64) + _jitter(seed, n, dim, jitter)
+    box = np.array(dims, dtype=np.float64)
+    offsets = np.array(list(itertools.product((-1, 0, 1), repeat=dim)), dtype=np.int64)
+    pts = (xyz[None, :, :] + offsets[:, None, :] * box).reshape(-1, dim)
+    node = np.tile(idx, len(offsets))
+    shift = np.repeat(offsets, n, axis=0)
+    simp = Delaunay(pts).simplices
+    cen = pts[simp].mean(axis=1)
+    keep = np.all((cen >= 0.0) & (cen < box), axis=1)
+    simp = simp[keep]
+    conn = node[simp].astype(np.int32)
+    sh = shift[simp].astype(np.int8)
+    # positive orientation: swap the first two vertices of negative simplices
+    v = pts[simp]
+    edges = v[:, 1:, :] - v[:, :1, :]
+    vol = np.linalg.det(edges)
+    neg = vol < 0
+    conn[neg, 0], conn[neg, 1] = conn[neg, 1].copy(), conn[neg, 0].copy()
+    sh[neg, 0], sh[neg, 1] = sh[neg, 1].copy(), sh[neg, 0].copy()
+    return dict(dim=dim, xyz=xyz, conn=conn, shift=sh, box=box, wall=np.zeros(n, np.uint8),
+                wall_normal=np.zeros((n, dim)))
+
+
 def mesh_summary(mesh: dict) -> dict:
     return dict(dim=mesh["dim"], n_nodes=int(mesh["xyz"].shape[0]),
                 n_elems=int(mesh["conn"].shape[0]),

@@ -120,3 +120,17 @@ def test_layout_padding_and_workspace():
     c3.upload_mesh(0, grid_mesh_3d(4, 4, 4))
     info = c3.layout_info()
     assert info["ell_width"] == 15 and info["cg_iters"] == 17
+
+
+def test_valence_above_widest_layout_rejected():
+    """A 3-D Delaunay mesh with a node of valence 26 exceeds the widest ELL
+    layout (24 slots): the layout is refused with FEL_EINVAL."""
+    from paper_1608_01906_amd.inputs.mesh import delaunay_mesh
+    ctx = felbm.Context(19)
+    ctx.upload_mesh(0, delaunay_mesh((10, 10, 10), seed=1618))
+    with pytest.raises(felbm.FelError) as ei:
+        ctx.layout_info()
+    assert ei.value.status == felbm.FEL_EINVAL
+    ok = felbm.Context(19)
+    ok.upload_mesh(0, delaunay_mesh((10, 10, 10), seed=1614))
+    assert ok.layout_info()["ell_width"] == 24

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from paper_1608_01906_amd.inputs import grid_mesh_2d, grid_mesh_3d
+from paper_1608_01906_amd.inputs.mesh import delaunay_mesh
 from tests._bruteforce import dense_operators, stream_matrix
 
 D2Q9 = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]], float)
@@ -24,7 +25,10 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 def _meshes():
     return [("periodic2d", grid_mesh_2d(6, 5, seed=11), 9),
             ("walled2d", grid_mesh_2d(5, 6, wall_y=True, seed=12), 9),
-            ("periodic3d", grid_mesh_3d(3, 3, 4, seed=13), 19)]
+            ("periodic3d", grid_mesh_3d(3, 3, 4, seed=13), 19),
+            # unstructured (Delaunay) periodic meshes: irregular valence
+            ("delaunay2d", delaunay_mesh((6, 5), seed=14), 9),
+            ("delaunay3d", delaunay_mesh((4, 3, 4), seed=15), 19)]
 
 
 @pytest.fixture(scope="module", params=_meshes(), ids=lambda m: m[0])
