@@ -163,7 +163,14 @@ FEL_API fel_status fel_bind(fel_ctx* ctx, void* dev_ptr, size_t bytes, void* hip
 FEL_API fel_status fel_init_fields(fel_ctx* ctx, int inst, const fel_phys* phys, const double* rho,
                                    const double* u, const double* p);
 
-/* Advances every instance by n_steps time steps; asynchronous on the bound stream. */
+/* Advances every instance by n_steps time steps; asynchronous on the bound
+ * stream.  The first call also settles whatever schedule the options left
+ * to timing (fel_options.solver_batch, lds_staging, fused_reductions): it
+ * launches the candidates on the solve's scratch buffers and synchronizes
+ * the stream, so it must not be made while the caller captures that stream
+ * into a graph.  The library captures the step into a graph of its own on
+ * the first call and replays it afterwards (on a non-default stream and
+ * while not profiling). */
 FEL_API fel_status fel_step(fel_ctx* ctx, int n_steps);
 
 /* Waits for the stream and reports device conditions raised since the last
