@@ -1,0 +1,52 @@
+"""Device-side conditions reported through fel_sync, forced from the host
+(no kernel faults): the CG residual check and the non-finite state flag."""
+import numpy as np
+import pytest
+
+from paper_1608_01906_amd.inputs import droplet2d
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def felbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_01906_amd import felbm as F
+    F.load_library()
+    return F
+
+
+@pytest.mark.parametrize("fused", [1, 2])
+def test_cg_not_converged_is_reported(felbm, fused):
+    """One CG iteration cannot reach a 1e-12 relative residual: fel_sync
+    returns FEL_ENOTCONV (finalize-launch and fused checks alike), clears the
+    flag, and a fully iterated context reports nothing."""
+    w = droplet2d(32, radius=8.0)
+    ctx = felbm.from_workload(w, precision="fp64", cg_iters=1, cg_tol=1e-12, fused_reductions=fused)
+    ctx.step(2)
+    with pytest.raises(felbm.FelError) as ei:
+        ctx.sync()
+    assert ei.value.status == felbm.FEL_ENOTCONV
+    ctx.sync()                                   # the flag was cleared by the report
+    ctx.step(1)
+    assert ctx.sync(allow_notconv=True) == felbm.FEL_ENOTCONV
+    ok = felbm.from_workload(w, precision="fp64", fused_reductions=fused)
+    ok.step(2)
+    ok.sync()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_non_finite_state_is_reported(felbm, precision):
+    """A NaN planted in one population spreads through the step; fel_sync
+    returns FEL_ENONFINITE."""
+    w = droplet2d(32, radius=8.0)
+    ctx = felbm.from_workload(w, precision=precision)
+    st = ctx.get_state(0)
+    st[3, 100] = np.nan
+    ctx.set_state(0, st)
+    ctx.step(1)
+    with pytest.raises(felbm.FelError) as ei:
+        ctx.sync()
+    assert ei.value.status == felbm.FEL_ENONFINITE
