@@ -114,7 +114,9 @@ typedef struct {
                              sums them itself (D2Q9 layouts with instances of at most 1024 tiles,
                              else fel_bind returns FEL_EINVAL); 0 = chosen by timing both solves on
                              the bound layout before the first step (1 where fused is unavailable).
-                             Same results to rounding (the partial sums group rows differently) */
+                             Same results to rounding (the partial sums group rows differently).
+                             The lumped and Chebyshev mass modes reduce nothing: there the option is
+                             ignored and fel_tuning reads 1 after the first step */
 } fel_options;
 
 /* Physical parameters of one instance (Section 2.1).  rho_l is the heavy

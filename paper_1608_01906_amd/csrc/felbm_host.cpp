@@ -778,7 +778,7 @@ fel_status fel_bind(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
         return fail(c, FEL_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, c->ws_bytes);
     c->dev = static_cast<char*>(dev_ptr);
     c->stream = static_cast<hipStream_t>(hip_stream);
-    if (c->fused == 2 && !c->fused_ok)
+    if (c->fused == 2 && !c->fused_ok && c->opt.mass_mode == FEL_MASS_CONSISTENT)
         return fail(c, FEL_EINVAL, "fused reductions need a D2Q9 layout (ELL width 7 or 12) with at most %d "
                     "blocks of %d tiles per instance", kFusedMaxBlocks, kFusedTiles);
     set_pointers(c);
@@ -1040,6 +1040,9 @@ fel_status choose_fused(fel_ctx* c) {
     HIP_TRY(c, hipMemcpy(&saved, c->dev + c->off.status, 4, hipMemcpyDeviceToHost));
     hipEvent_t a = get_event(c), b = get_event(c);
     if (!a || !b) return fail(c, FEL_EDEVICE, "event creation failed");
+    // per-launch profiling events cannot be recorded inside a capture
+    const bool profiling = c->profiling;
+    c->profiling = false;
     fel_status st = FEL_OK;
     int best = 1;
     float best_ms = 0.0f;
@@ -1065,6 +1068,7 @@ fel_status choose_fused(fel_ctx* c) {
         if (mode == 1 || ms < best_ms) best = mode, best_ms = ms;
     }
     c->fused = st == FEL_OK ? best : 1;
+    c->profiling = profiling;
     c->event_pool.push_back(a);
     c->event_pool.push_back(b);
     if (st != FEL_OK) return st;

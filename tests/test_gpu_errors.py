@@ -50,3 +50,29 @@ def test_non_finite_state_is_reported(felbm, precision):
     with pytest.raises(felbm.FelError) as ei:
         ctx.sync()
     assert ei.value.status == felbm.FEL_ENONFINITE
+
+
+def test_profiling_from_the_first_step(felbm):
+    """Profiling switched on before the first step, so the schedule (the
+    reduction form included) is tuned while profiling: tuning completes,
+    every launch of the steps is counted, and the state agrees with an
+    unprofiled context (to FP32 rounding: the two may tune differently)."""
+    w = droplet2d(64)
+    a = felbm.from_workload(w, precision="fp32")
+    b = felbm.from_workload(w, precision="fp32")
+    a.profile(True)
+    a.step(3)
+    prof = a.profile_read()
+    a.profile(False)
+    a.sync()
+    b.step(3)
+    b.sync()
+    t = a.tuning()
+    print("schedule tuned while profiling:", t, flush=True)
+    assert t["fused"] in (1, 2)
+    k = a.layout_info()["cg_iters"]
+    assert prof["stream"][0] == 3 and prof["collide"][0] == 3 and prof["cg_a"][0] == 3 * k
+    ra, rb = a.read_fields(0), b.read_fields(0)
+    for name in ("rho", "u", "p", "C"):
+        y = rb[name]
+        np.testing.assert_allclose(ra[name], y, rtol=0, atol=2e-5 * max(1.0, float(np.abs(y).max())))

@@ -138,13 +138,18 @@ def test_fused_matches_finalize_path(felbm):
 
 def test_fused_unavailable_cases(felbm):
     """3-D layouts and instances above 1024 tiles cannot take the fused path:
-    asking for it is an error at bind, the tuner falls back to finalize
-    launches."""
+    asking for it with the CG solve is an error at bind, the tuner falls
+    back to finalize launches."""
     from paper_1608_01906_amd.inputs import grid_mesh_2d, droplet_instance, Workload
     w3 = droplet3d(11, radius=3.0, xi=3.0)
     with pytest.raises(felbm.FelError):
         felbm.from_workload(w3, fused_reductions=2)
     ctx = felbm.from_workload(w3)
+    ctx.step(1)
+    ctx.sync()
+    assert ctx.tuning()["fused"] == 1
+    # the reduction-free Chebyshev solve ignores the option
+    ctx = felbm.from_workload(w3, mass_mode=2, fused_reductions=2)
     ctx.step(1)
     ctx.sync()
     assert ctx.tuning()["fused"] == 1
