@@ -592,7 +592,9 @@ static fel_status plan_layout(fel_ctx* c) {
         for (int64_t t = 0; t < tiles; t++) c->tile_inst.push_back(i);
         rows += tiles * TILE;
     }
-    if (rows >= ((int64_t)1 << 31)) return fail(c, FEL_EINVAL, "too many rows");
+    // gathers address one population's vector with 32-bit byte offsets
+    if (rows >= ((int64_t)1 << 31) || rows * elem_size(c->opt.precision) >= ((int64_t)1 << 32))
+        return fail(c, FEL_EINVAL, "too many rows (%lld)", (long long)rows);
     c->R = rows;
     c->ntiles = (int)(rows / TILE);
     build_halos(c);
