@@ -111,12 +111,12 @@ def measured_traffic(workload: str, precision: str, mass_mode: int, kernel: str,
     return lookup_traffic(rec, kernel, name)
 
 
-def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="channel2d"):
+def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="channel2d", node_order=0):
     import torch
     from paper_1608_01906_amd import felbm
     N = w.n_nodes
     P = 2 * w.lattice
-    ctx = felbm.from_workload(w, precision=precision, device="cuda:0", mass_mode=mass_mode)
+    ctx = felbm.from_workload(w, precision=precision, device="cuda:0", mass_mode=mass_mode, node_order=node_order)
     info = ctx.layout_info()
     ctx.step(warmup)
     ctx.sync(allow_notconv=True)
@@ -203,6 +203,8 @@ def main():
                     help="skip the run with the mass matrix solved by Chebyshev iteration")
     ap.add_argument("--mass-mode", type=int, default=0, choices=[0, 1, 2],
                     help="mass solve of the headline run: 0 consistent (CG), 1 lumped, 2 consistent (Chebyshev)")
+    ap.add_argument("--node-order", type=int, default=0, choices=[0, 1],
+                    help="device row order: 0 the workload's node order, 1 Z-order curve")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -228,7 +230,7 @@ def main():
     N = w.n_nodes
     P = 2 * w.lattice
     head, ctx_head = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps,
-                             mass_mode=args.mass_mode, workload=args.workload)
+                             mass_mode=args.mass_mode, workload=args.workload, node_order=args.node_order)
     mass = {0: f"consistent, CG x{head['cg_iters']}", 1: "lumped",
             2: f"consistent, Chebyshev x{head['cg_iters']}"}[args.mass_mode]
     out = {
@@ -246,7 +248,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": DESCRIPTIONS.get(args.workload, w.name), "instances": len(w.instances),
                    "nodes": N, "populations": P, "precision": args.precision,
-                   "mass": mass, "dt": inst.phys.dt},
+                   "mass": mass, "dt": inst.phys.dt,
+                   "node_order": ("workload", "z-curve")[args.node_order]},
         "roofline": head["roofline"],
         "step_algorithmic_gbs": head["step_algorithmic_gbs"],
         "step_frac": head["step_frac"],
@@ -259,13 +262,13 @@ def main():
     ctx64 = None
     if not args.no_fp64 and args.precision != "fp64":
         r64, ctx64 = run_gpu(w, "fp64", args.steps, args.warmup, args.profile_steps, mass_mode=args.mass_mode,
-                             workload=args.workload)
+                             workload=args.workload, node_order=args.node_order)
         out["fp64_plain"] = {k: r64[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
                                                  "step_frac", "event_ms_per_step")}
         out["speedup_vs_fp64_plain"] = head["value"] / r64["value"]
     if not args.no_chebyshev and args.mass_mode != 2:
         rch, _ = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, mass_mode=2,
-                         workload=args.workload)
+                         workload=args.workload, node_order=args.node_order)
         out["chebyshev_solve"] = {k: rch[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
                                                       "step_frac", "event_ms_per_step", "schedule")}
     if not args.no_cpu_baseline:
@@ -275,7 +278,8 @@ def main():
         ref = orc.fields()
         errs = {}
         for prec in [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"]):
-            c = felbm.from_workload(w, precision=prec, device="cuda:0", mass_mode=args.mass_mode)
+            c = felbm.from_workload(w, precision=prec, device="cuda:0", mass_mode=args.mass_mode,
+                                    node_order=args.node_order)
             c.step(s_steps)
             c.sync(allow_notconv=True)
             errs[prec] = {k: float(f"{v:.3e}") for k, v in compare_fields(c.read_fields(0), ref, inst).items()}

@@ -105,6 +105,9 @@ typedef struct {
     int lds_staging;      /* mass-solve kernels read neighbour values 1 = by direct gathers from
                              memory, 2 = from a per-tile stage in LDS (the tile's rows and its halo
                              loaded once per population, coalesced), 0 = chosen per kernel by timing.
+                             Staging needs tile halos of at most 1024 rows and two stages of the
+                             population batch within 60 KB of LDS; a forced 2 that does not fit makes
+                             the first fel_step return FEL_EINVAL (0 then keeps direct gathers).
                              Every schedule computes the same sums in the same order; results agree
                              to rounding (the staged and direct forms may contract multiply-adds
                              differently) */

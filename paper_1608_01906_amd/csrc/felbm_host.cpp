@@ -833,10 +833,12 @@ hipError_t timed(fel_ctx* c, int cls, F&& launch) {
 }
 
 // Whether a class runs its LDS-staged kernel, and whether batch ch fits the
-// staged kernel's dynamic LDS (ch stage rows of sw values).
+// staged kernel (its dynamic LDS holds 2 ch stage rows of sw values, and a
+// thread stages at most kHaloRounds halo entries).
 bool staged(const fel_ctx* c, int cls) { return c->stage[cls] == 2; }
 bool stage_fits(const fel_ctx* c, int ch) {
-    return (size_t)ch * c->sw * (size_t)elem_size(c->opt.precision) <= 60 * 1024;
+    return c->hmax <= kHaloRounds * TILE &&
+           2 * (size_t)ch * c->sw * (size_t)elem_size(c->opt.precision) <= (size_t)kStageBytes;
 }
 
 hipError_t enqueue_solve(fel_ctx* c) {
@@ -962,7 +964,8 @@ fel_status tune_schedule(fel_ctx* c) {
         }
         if (st != FEL_OK) break;
         if (best_b == 0) {  // a fixed staged batch whose stage does not fit
-            st = fail(c, FEL_EINVAL, "LDS stage of %d rows of %d values does not fit", c->batch[cls], c->sw);
+            st = fail(c, FEL_EINVAL, "LDS stage of 2 x %d rows of %d values (halo %d) does not fit",
+                      c->batch[cls], c->sw, c->hmax);
             break;
         }
         c->batch[cls] = best_b;

@@ -129,6 +129,8 @@ hipError_t launch_cg_init_fused(const DevLayout& L, int batch, hipStream_t s);
 hipError_t launch_cg_a_fused(const DevLayout& L, int it, int batch, hipStream_t s);
 hipError_t launch_cg_b_fused(const DevLayout& L, int it, int batch, hipStream_t s);
 hipError_t launch_fused_check(const DevLayout& L, hipStream_t s);
+constexpr int kHaloRounds = 4;       // LDS staging: halo entries per thread at most (halo <= 4 TILE)
+constexpr int kStageBytes = 60 * 1024;  // LDS staging: dynamic LDS per block at most (2 batches of sw rows)
 constexpr int kFusedTiles = 4;       // tiles per fused-reduction block
 constexpr int kFusedMaxBlocks = 256; // per instance (one round of loads per lane in the prologue)
 // Chebyshev solve: first launch writes x_0 to buffer out0 and x_1 to the

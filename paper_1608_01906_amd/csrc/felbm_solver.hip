@@ -561,6 +561,12 @@ __global__ __launch_bounds__(64) void k_fused_check(DevLayout L) {
 // row reads its W neighbours from LDS through the 16-bit local columns.
 // A wavefront thus issues 1 + halo/TILE global loads per population and
 // vector instead of W gathers.  CH populations per pass, rows sw apart.
+// The stage is double-buffered: the loads of the next pass are issued
+// right after the barrier that publishes the current one, so they are in
+// flight while the rows read LDS, and one barrier per pass suffices (a
+// buffer is rewritten two passes later, after every row has passed the
+// intervening barrier).  Each thread stages at most kHaloRounds halo
+// entries (halo <= kHaloRounds * TILE; the host checks).
 
 template <int W>
 struct LocalCols {
@@ -580,10 +586,12 @@ __device__ __forceinline__ T lds_row_product(const T* mv, const LocalCols<W>& l,
     return acc;
 }
 
-// Drives the passes: body.stage(j, g) is the staged value of population j
-// at global row g; body.keep(j, own) loads what the row keeps in registers
-// for population j; body.use(j, stage_row, own) finishes the row and
-// returns its dot-product term.
+// Drives the passes: body.pre(g) is a per-row value the staged values of
+// row g need for every population (loaded once per tile); body.stage(j, g,
+// pre) is the staged value of population j at global row g; body.keep(j,
+// own) loads what the row keeps in registers for population j;
+// body.use(j, stage_row, own) finishes the row and returns its dot-product
+// term.  sh holds 2 CH stage rows.
 template <typename T, int NP, int CH, class Body>
 __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int tile, int row, T* sh,
                                            TileReducer<NP>* red) {
@@ -591,36 +599,57 @@ __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int t
     const int sw = L.sw;
     const int hb = L.halo_ptr[tile], hn = L.halo_ptr[tile + 1] - hb;
     const int lr = threadIdx.x;
+    int hg[kHaloRounds];
+    T pre_h[kHaloRounds];
+#pragma unroll
+    for (int i = 0; i < kHaloRounds; i++) {
+        const int h = lr + i * TILE;
+        hg[i] = h < hn ? L.halo_col[hb + h] : -1;
+        pre_h[i] = hg[i] >= 0 ? body.pre(hg[i]) : T(0);
+    }
+    const T pre_own = body.pre(row);
+    typename Body::Own own[2][CH];
+    T v[CH], vh[kHaloRounds][CH];
+    auto fetch = [&](int j0, typename Body::Own* o) {
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            body.keep(j0 + u, o[u]);
+            v[u] = body.stage(j0 + u, row, pre_own);
+        }
+#pragma unroll
+        for (int i = 0; i < kHaloRounds; i++) {
+            if (hg[i] >= 0) {
+#pragma unroll
+                for (int u = 0; u < CH; u++) vh[i][u] = body.stage(j0 + u, hg[i], pre_h[i]);
+            }
+        }
+    };
+    fetch(0, own[0]);
     double dots[RG];
 #pragma unroll
     for (int j0 = 0; j0 < NP; j0 += CH) {
-        typename Body::Own own[CH];
-        T v[CH];
+        const int p = (j0 / CH) & 1;
+        T* buf = sh + p * CH * sw;
 #pragma unroll
-        for (int u = 0; u < CH; u++) {
-            body.keep(j0 + u, own[u]);
-            v[u] = body.stage(j0 + u, row);
-        }
+        for (int u = 0; u < CH; u++) buf[u * sw + lr] = v[u];
 #pragma unroll
-        for (int u = 0; u < CH; u++) sh[u * sw + lr] = v[u];
-        for (int h = lr; h < hn; h += TILE) {
-            const int g = L.halo_col[hb + h];
+        for (int i = 0; i < kHaloRounds; i++) {
+            if (hg[i] >= 0) {
 #pragma unroll
-            for (int u = 0; u < CH; u++) v[u] = body.stage(j0 + u, g);
-#pragma unroll
-            for (int u = 0; u < CH; u++) sh[u * sw + TILE + h] = v[u];
+                for (int u = 0; u < CH; u++) buf[u * sw + TILE + i * TILE + lr] = vh[i][u];
+            }
         }
         __syncthreads();
+        if (j0 + CH < NP) fetch(j0 + CH, own[p ^ 1]);
 #pragma unroll
         for (int u = 0; u < CH; u++) {
             const int j = j0 + u;
-            const double d = body.use(j, sh + u * sw, own[u]);
+            const double d = body.use(j, buf + u * sw, own[p][u]);
             if constexpr (Body::kDots) {
                 dots[j % RG] = d;
                 if (j % RG == RG - 1) red->add_group(j - (RG - 1), dots);
             }
         }
-        __syncthreads();
     }
 }
 
@@ -635,7 +664,8 @@ struct CgInitStaged {
     T *X, *Rv;
     int64_t R;
     int row;
-    __device__ __forceinline__ T stage(int j, int g) const { return rhs[(int64_t)j * R + g] * minv[g]; }
+    __device__ __forceinline__ T pre(int g) const { return minv[g]; }
+    __device__ __forceinline__ T stage(int j, int g, T mg) const { return rhs[(int64_t)j * R + g] * mg; }
     __device__ __forceinline__ void keep(int j, Own& o) const { o.rhs = rhs[(int64_t)j * R + row]; }
     __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
         const T acc = lds_row_product<T, W>(mv, l, st);
@@ -659,12 +689,13 @@ struct CgAStaged {
     const double* beta;
     int64_t R;
     int row;
-    __device__ __forceinline__ T stage(int j, int g) const {
+    __device__ __forceinline__ T pre(int g) const { return minv[g]; }
+    __device__ __forceinline__ T stage(int j, int g, T mg) const {
         const int64_t i = (int64_t)j * R + g;
         if constexpr (FIRST)
-            return Rv[i] * minv[g];
+            return Rv[i] * mg;
         else
-            return Rv[i] * minv[g] + (T)beta[j] * Pold[i];
+            return Rv[i] * mg + (T)beta[j] * Pold[i];
     }
     __device__ __forceinline__ void keep(int, Own&) const {}
     __device__ __forceinline__ double use(int j, const T* st, const Own&) const {
@@ -687,7 +718,8 @@ struct CgBStaged {
     const double* alpha;
     int64_t R;
     int row;
-    __device__ __forceinline__ T stage(int j, int g) const { return Pn[(int64_t)j * R + g]; }
+    __device__ __forceinline__ T pre(int) const { return T(0); }
+    __device__ __forceinline__ T stage(int j, int g, T) const { return Pn[(int64_t)j * R + g]; }
     __device__ __forceinline__ void keep(int j, Own& o) const {
         const int64_t i = (int64_t)j * R + row;
         o.x = X[i];
@@ -716,7 +748,8 @@ struct ChebFirstStaged {
     T gamma;
     int64_t R;
     int row;
-    __device__ __forceinline__ T stage(int j, int g) const { return rhs[(int64_t)j * R + g] * minv[g]; }
+    __device__ __forceinline__ T pre(int g) const { return minv[g]; }
+    __device__ __forceinline__ T stage(int j, int g, T mg) const { return rhs[(int64_t)j * R + g] * mg; }
     __device__ __forceinline__ void keep(int j, Own& o) const { o.rhs = rhs[(int64_t)j * R + row]; }
     __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
         const T acc = lds_row_product<T, W>(mv, l, st);
@@ -740,7 +773,8 @@ struct ChebStaged {
     T omega, gamma;
     int64_t R;
     int row;
-    __device__ __forceinline__ T stage(int j, int g) const { return xk[(int64_t)j * R + g]; }
+    __device__ __forceinline__ T pre(int) const { return T(0); }
+    __device__ __forceinline__ T stage(int j, int g, T) const { return xk[(int64_t)j * R + g]; }
     __device__ __forceinline__ void keep(int j, Own& o) const {
         const int64_t i = (int64_t)j * R + row;
         o.b = rhs[i];
@@ -870,9 +904,9 @@ __global__ __launch_bounds__(TILE) void k_lumped(DevLayout L, int tile_begin) {
 // dispatch
 
 // dynamic LDS a staged launch may use
-constexpr size_t kMaxStageBytes = 60 * 1024;  // plus the static reducer buffer
+constexpr size_t kMaxStageBytes = kStageBytes;  // plus the static reducer buffer
 
-// Launches kernel K<T, W, NP, CH> (or, when staged, K_lds with ch * sw
+// Launches kernel K<T, W, NP, CH> (or, when staged, K_lds with 2 ch sw
 // values of dynamic LDS) for the context's value type and the population
 // batch ch (1, 2 or 4).
 #define FEL_SOLVER_LAUNCH_T(K, T, SH, ch, s, nt, ...)                                    \
@@ -888,8 +922,9 @@ constexpr size_t kMaxStageBytes = 60 * 1024;  // plus the static reducer buffer
     do {                                                                              \
         const bool f64_ = L.precision == 0;                                           \
         if (staged) {                                                                 \
-            const size_t sh_ = (size_t)(ch) * L.sw * (f64_ ? 8 : 4);                  \
-            if (sh_ > kMaxStageBytes) return hipErrorInvalidValue;                    \
+            const size_t sh_ = 2 * (size_t)(ch) * L.sw * (f64_ ? 8 : 4);              \
+            if (sh_ > kMaxStageBytes || L.sw > TILE + kHaloRounds * TILE)             \
+                return hipErrorInvalidValue;                                          \
             if (f64_) FEL_SOLVER_LAUNCH_T(K##_lds, double, sh_, ch, s, nt, __VA_ARGS__); \
             else FEL_SOLVER_LAUNCH_T(K##_lds, float, sh_, ch, s, nt, __VA_ARGS__);       \
         } else {                                                                      \
