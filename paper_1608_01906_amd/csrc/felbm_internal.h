@@ -132,7 +132,7 @@ hipError_t launch_fused_check(const DevLayout& L, hipStream_t s);
 constexpr int kHaloRounds = 4;       // LDS staging: halo entries per thread at most (halo <= 4 TILE)
 constexpr int kStageBytes = 60 * 1024;  // LDS staging: dynamic LDS per block at most (2 batches of sw rows)
 constexpr int kFusedTiles = 4;       // tiles per fused-reduction block
-constexpr int kFusedMaxBlocks = 256; // per instance (one round of loads per lane in the prologue)
+constexpr int kFusedMaxBlocks = 256; // per instance (a lane of a fused block loads at most 4 of its partials)
 // Chebyshev solve: first launch writes x_0 to buffer out0 and x_1 to the
 // other (0 = X, 1 = Pa); each later launch reads x_k from buffer cur.
 hipError_t launch_cheb_first(const DevLayout& L, int tile_begin, int ntiles, int out0, double gamma, int batch,

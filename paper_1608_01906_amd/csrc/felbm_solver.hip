@@ -439,20 +439,36 @@ constexpr int FB_WAVES = FB_THREADS / 64;
     const int inst = fb.z;                                            \
     const int pidx = L.params[inst].fb_begin + fb.w
 
-// tot[j] = sum over the instance's blocks of src[j][block], j < NP
+// tot[j] = sum over the instance's blocks of src[j][block], j < NP.  Wave
+// w sums population w: lane l holds blocks l, l + 64, ... (at most
+// kFusedMaxBlocks / 64 of them).  load() issues those loads at kernel start,
+// ahead of the row loads, so they have arrived when reduce() needs them
+// before the first population is used.
 template <int NP>
-__device__ __forceinline__ void fused_totals(const DevLayout& L, const double* src, int inst, double* tot) {
-    const InstParams& P = L.params[inst];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j = wave; j < NP; j += FB_WAVES) {
-        const double* p = src + (int64_t)j * L.nfb + P.fb_begin;
-        double s = 0.0;
-        for (int b = lane; b < P.fb_count; b += 64) s += p[b];
-        s = wave_sum(s);
-        if (lane == 0) tot[j] = s;
+struct FusedTotals {
+    static_assert(NP <= FB_WAVES, "one population per wave");
+    static constexpr int K = kFusedMaxBlocks / 64;
+    double v[K];
+    __device__ __forceinline__ void load(const DevLayout& L, const double* src, int inst) {
+        const InstParams& P = L.params[inst];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const double* p = src + (int64_t)(wave < NP ? wave : 0) * L.nfb + P.fb_begin;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int b = lane + 64 * k;
+            v[k] = (wave < NP && b < P.fb_count) ? p[b] : 0.0;
+        }
     }
-    __syncthreads();
-}
+    __device__ __forceinline__ void reduce(double* tot) const {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; k++) s += v[k];
+        s = wave_sum(s);
+        if (lane == 0 && wave < NP) tot[wave] = s;
+        __syncthreads();
+    }
+};
 
 // Every thread of a fused block runs the row pipeline (spare waves of an
 // instance's last, short block on its first tile with stores masked), so
@@ -480,8 +496,10 @@ __global__ __launch_bounds__(FB_THREADS) void k_cg_a_fused(DevLayout L, int it) 
     FEL_FUSED_LAYOUT();
     __shared__ double tot[NP], bet[NP];
     const int cur = it & 1;
+    FusedTotals<NP> rz;
+    rz.load(L, L.fpart0, inst);  // r.z of the current residual
     auto scalars = [&] {
-        fused_totals<NP>(L, L.fpart0, inst, tot);  // r.z of the current residual
+        rz.reduce(tot);
         if (threadIdx.x < NP) {
             const int j = threadIdx.x;
             if (fb.w == 0) {
@@ -515,8 +533,10 @@ template <typename T, int W, int NP, int CH>
 __global__ __launch_bounds__(FB_THREADS) void k_cg_b_fused(DevLayout L, int it) {
     FEL_FUSED_LAYOUT();
     __shared__ double tot[NP], alp[NP];
+    FusedTotals<NP> pq;
+    pq.load(L, L.fpart1, inst);  // p.q
     auto scalars = [&] {
-        fused_totals<NP>(L, L.fpart1, inst, tot);  // p.q
+        pq.reduce(tot);
         if (threadIdx.x < NP) {
             const int j = threadIdx.x;
             const double rz = L.srz[((int64_t)(it & 1) * L.ninst + inst) * NP + j];
