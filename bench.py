@@ -201,6 +201,8 @@ def main():
                     help="first copy this many MiB device-to-device (HBM counter calibration)")
     ap.add_argument("--no-chebyshev", action="store_true",
                     help="skip the run with the mass matrix solved by Chebyshev iteration")
+    ap.add_argument("--no-lumped", action="store_true",
+                    help="skip the run with the lumped mass matrix (the paper's own approximation)")
     ap.add_argument("--mass-mode", type=int, default=0, choices=[0, 1, 2],
                     help="mass solve of the headline run: 0 consistent (CG), 1 lumped, 2 consistent (Chebyshev)")
     ap.add_argument("--node-order", type=int, default=0, choices=[0, 1],
@@ -271,6 +273,11 @@ def main():
                          workload=args.workload, node_order=args.node_order)
         out["chebyshev_solve"] = {k: rch[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
                                                       "step_frac", "event_ms_per_step", "schedule")}
+    if not args.no_lumped and args.mass_mode != 1:
+        rlu, _ = run_gpu(w, args.precision, args.steps, args.warmup, args.profile_steps, mass_mode=1,
+                         workload=args.workload, node_order=args.node_order)
+        out["lumped_mass"] = {k: rlu[k] for k in ("value", "ms_per_step", "roofline", "step_algorithmic_gbs",
+                                                  "step_frac", "event_ms_per_step")}
     if not args.no_cpu_baseline:
         from paper_1608_01906_amd import felbm
         cb, orc, s_steps = cpu_baseline(w, mass_mode=args.mass_mode)
