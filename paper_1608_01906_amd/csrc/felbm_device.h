@@ -165,6 +165,13 @@ struct TileReducer {
     __shared__ double NAME##_buf[NW][NP];             \
     TileReducer<NP, NW> NAME(NAME##_buf)
 
+// Column of ELL slot k of a row.  Slot 0 is the diagonal in every pattern
+// row (padding rows included), so it is the row itself and is not loaded;
+// with k a compile-time constant the test folds away.
+__device__ __forceinline__ int ell_col(const DevLayout& L, int k, int64_t row) {
+    return k == 0 ? (int)row : L.col[k * L.R + row];
+}
+
 // gathers through a uniform base and a 32-bit byte offset
 template <typename T>
 __device__ __forceinline__ T gat(const T* base, int idx) {

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(TILE) void k_stream_plain(DevLayout L, int tile_beg
     for (int j = 0; j < NP; j++) acc[j] = 0.0;
 #pragma unroll
     for (int k = 0; k < W; k++) {
-        const int64_t c = L.col[k * R + row];
+        const int64_t c = ell_col(L, k, row);
         double b[NB];
 #pragma unroll
         for (int n = 0; n < NB; n++) b[n] = B[((int64_t)n * W + k) * R + row];
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(TILE) void k_grad(DevLayout L, int tile_begin) {
     for (int r = 0; r < D; r++) g[r] = 0;
 #pragma unroll
     for (int k = 0; k < W; k++) {
-        const T v = rho[L.col[k * R + row]];
+        const T v = rho[ell_col(L, k, row)];
 #pragma unroll
         for (int r = 0; r < D; r++) g[r] += B[((int64_t)r * W + k) * R + row] * v;
     }
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(TILE) void k_div(DevLayout L, int tile_begin) {
     for (int r = 0; r < D; r++) S[r] = 0;
 #pragma unroll
     for (int k = 0; k < W; k++) {
-        const int64_t c = L.col[k * R + row];
+        const int64_t c = ell_col(L, k, row);
         T gk[D], Gk[D];
         T E = 0;
 #pragma unroll
@@ -228,7 +228,7 @@ __device__ __forceinline__ void gather_gradmu(const DevLayout& L, int64_t row, d
     for (int r = 0; r < 3; r++) gm[r] = 0.0;
 #pragma unroll
     for (int k = 0; k < W; k++) {
-        const double v = mu[L.col[k * R + row]];
+        const double v = mu[ell_col(L, k, row)];
 #pragma unroll
         for (int r = 0; r < D; r++) gm[r] += B[((int64_t)r * W + k) * R + row] * v;
     }
@@ -407,8 +407,10 @@ __global__ __launch_bounds__(TILE) void k_stream_dev(DevLayout L, int tile_begin
     float acc[NP];
 #pragma unroll
     for (int j = 0; j < NP; j++) acc[j] = 0.0f;
+    // slot 0 is the row itself, whose differences are exactly 0: it adds
+    // nothing to the sums, so it is skipped
 #pragma unroll
-    for (int k = 0; k < W; k++) {
+    for (int k = 1; k < W; k++) {
         const int c = L.col[k * R + row];
         float b[NB];
 #pragma unroll
@@ -479,7 +481,7 @@ __device__ __forceinline__ void gather_grad_of(const DevLayout& L, const void* f
     for (int r = 0; r < 3; r++) gm[r] = 0;
 #pragma unroll
     for (int k = 0; k < W; k++) {
-        const T v = gat(f, L.col[k * R + row]);
+        const T v = gat(f, ell_col(L, k, row));
 #pragma unroll
         for (int r = 0; r < D; r++) gm[r] += B[((int64_t)r * W + k) * R + row] * v;
     }

@@ -125,7 +125,10 @@ __device__ __forceinline__ void run_rows(Body& body, Red* red, Hook before_use =
     const int row = tile * TILE + threadIdx.x
 
 // Row operands shared by the solver bodies: ELL columns and mass values of
-// the row, and (MI) the inverse lumped mass at the columns.
+// the row, and (MI) the inverse lumped mass at the columns.  Slot 0 holds
+// the diagonal (the host builds every pattern row diagonal-first, padding
+// rows included), so its column is the row itself: it is not loaded, and
+// the bodies take its value from the row's own load instead of a gather.
 template <typename T, int W, bool MI>
 struct RowOps {
     int c[W];
@@ -133,13 +136,16 @@ struct RowOps {
     T mrow;
     __device__ __forceinline__ void load(const DevLayout& L, int64_t R, int row) {
         const T* minv = reinterpret_cast<const T*>(L.minv);
+        mrow = minv[row];
+        c[0] = row;
+        mv[0] = ld<T>(L.Mval, row);
+        if constexpr (MI) mi[0] = mrow;
 #pragma unroll
-        for (int k = 0; k < W; k++) {
+        for (int k = 1; k < W; k++) {
             c[k] = L.col[k * R + row];
             mv[k] = ld<T>(L.Mval, k * R + row);
             if constexpr (MI) mi[k] = gat(minv, c[k]);
         }
-        mrow = minv[row];
     }
 };
 
@@ -156,9 +162,10 @@ struct CgInitRows {
     bool live = true;  // false: a fused block's spare wave (loads only, no stores, zero terms)
     __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* b = rhs + (int64_t)j * R;
-#pragma unroll
-        for (int k = 0; k < W; k++) r.g[k] = gat(b, o.c[k]);
         r.own = b[row];
+        r.g[0] = r.own;
+#pragma unroll
+        for (int k = 1; k < W; k++) r.g[k] = gat(b, o.c[k]);
     }
     __device__ __forceinline__ double use(int j, const Regs& r) const {
         T acc = 0;
@@ -188,14 +195,16 @@ struct CgARows {
     bool live = true;
     __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* rv = Rv + (int64_t)j * R;
-#pragma unroll
-        for (int k = 0; k < W; k++) r.g[k] = gat(rv, o.c[k]);
         r.own = rv[row];
+        r.g[0] = r.own;
+#pragma unroll
+        for (int k = 1; k < W; k++) r.g[k] = gat(rv, o.c[k]);
         if constexpr (!FIRST) {
             const T* po = Pold + (int64_t)j * R;
-#pragma unroll
-            for (int k = 0; k < W; k++) r.h[k] = gat(po, o.c[k]);
             r.ownp = po[row];
+            r.h[0] = r.ownp;
+#pragma unroll
+            for (int k = 1; k < W; k++) r.h[k] = gat(po, o.c[k]);
         }
     }
     __device__ __forceinline__ double use(int j, const Regs& r) const {
@@ -230,9 +239,10 @@ struct CgBRows {
     bool live = true;
     __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* p = Pn + (int64_t)j * R;
-#pragma unroll
-        for (int k = 0; k < W; k++) r.g[k] = gat(p, o.c[k]);
         r.own = p[row];
+        r.g[0] = r.own;
+#pragma unroll
+        for (int k = 1; k < W; k++) r.g[k] = gat(p, o.c[k]);
         const int64_t i = (int64_t)j * R + row;
         r.x = X[i];
         r.r = Rv[i];
@@ -337,9 +347,10 @@ struct ChebFirstRows {
     int row;
     __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* b = rhs + (int64_t)j * R;
-#pragma unroll
-        for (int k = 0; k < W; k++) r.g[k] = gat(b, o.c[k]);
         r.own = b[row];
+        r.g[0] = r.own;
+#pragma unroll
+        for (int k = 1; k < W; k++) r.g[k] = gat(b, o.c[k]);
     }
     __device__ __forceinline__ double use(int j, const Regs& r) const {
         T acc = 0;
@@ -365,9 +376,10 @@ struct ChebRows {
     int row;
     __device__ __forceinline__ void load(int j, Regs& r) const {
         const T* x = xk + (int64_t)j * R;
-#pragma unroll
-        for (int k = 0; k < W; k++) r.g[k] = gat(x, o.c[k]);
         r.own = x[row];
+        r.g[0] = r.own;
+#pragma unroll
+        for (int k = 1; k < W; k++) r.g[k] = gat(x, o.c[k]);
         const int64_t i = (int64_t)j * R + row;
         r.b = rhs[i];
         r.xp = xp[i];
@@ -592,8 +604,9 @@ template <int W>
 struct LocalCols {
     int lc[W];
     __device__ __forceinline__ void load(const DevLayout& L, int64_t R, int row) {
+        lc[0] = row % TILE;  // slot 0: the row itself
 #pragma unroll
-        for (int k = 0; k < W; k++) lc[k] = L.lcol[k * R + row];
+        for (int k = 1; k < W; k++) lc[k] = L.lcol[k * R + row];
     }
 };
 
