@@ -41,15 +41,17 @@ def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, 
                  first_frac: float = 0.0) -> float:
     """Algorithmic HBM bytes per node row of one launch of a kernel class:
     every operand read or written once (gathers of neighbour values served
-    by cache), pattern = 4-byte column index per slot.  s = operator/vector
-    value size, sp = stored population size, dev = deviation storage with
-    two 4-byte node references."""
+    by cache), pattern = 4-byte column index per off-diagonal slot (slot 0
+    is the row itself).  s = operator/vector value size, sp = stored
+    population size, dev = deviation storage with two 4-byte node
+    references, where streaming works on differences to the row's own value
+    and needs no diagonal coefficients."""
     NP = 2 * (Q - 1)
     P = 2 * Q
-    pat = W * 4
+    pat = (W - 1) * 4
     ref = 8 if dev else 0
     if cls == "stream":
-        return NP * sp + ref + pat + NB * W * s + NP * s
+        return NP * sp + ref + pat + NB * (W - 1 if dev else W) * s + NP * s
     if cls == "cg_init":
         return 3 * NP * s + pat + W * s + s
     if cls == "cg_a":

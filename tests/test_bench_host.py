@@ -31,14 +31,14 @@ D3 = dict(Q=19, D=3, W=15, NB=9, s=4, sp=4, dev=True)
 
 
 @pytest.mark.parametrize("cls,per_row", [
-    # 16 moving populations of 4 bytes; pattern 7 x 4 B; mass values 7 x 4 B; 1/m 4 B
-    ("cg_b", 5 * 64 + 28 + 28 + 4),          # read p x r, write x r
-    ("cg_a", 3 * 64 + 28 + 28 + 4),          # read r p_old, write p_new
-    ("cg_init", 3 * 64 + 28 + 28 + 4),       # read rhs, write x r
-    ("cheb", 4 * 64 + 28 + 28 + 4),          # read x_k rhs x_{k-1}, write x_{k+1}
+    # 16 moving populations of 4 bytes; pattern 6 off-diagonal x 4 B; mass values 7 x 4 B; 1/m 4 B
+    ("cg_b", 5 * 64 + 24 + 28 + 4),          # read p x r, write x r
+    ("cg_a", 3 * 64 + 24 + 28 + 4),          # read r p_old, write p_new
+    ("cg_init", 3 * 64 + 24 + 28 + 4),       # read rhs, write x r
+    ("cheb", 4 * 64 + 24 + 28 + 4),          # read x_k rhs x_{k-1}, write x_{k+1}
     ("lumped", 2 * 64 + 4),
-    # 16 stored deviations + 2 references, pattern, 5 x 7 basis values, 16 rhs values
-    ("stream", 64 + 8 + 28 + 5 * 7 * 4 + 64),
+    # 16 stored deviations + 2 references, pattern, 5 x 6 off-diagonal basis values, 16 rhs values
+    ("stream", 64 + 8 + 24 + 5 * 6 * 4 + 64),
 ])
 def test_channel_bytes_per_row(cls, per_row):
     assert bench.kernel_bytes(cls, **CH) == per_row
@@ -48,19 +48,20 @@ def test_bytes_per_launch_match_the_reported_figures():
     """The per-launch figures quoted with the profiles: fused cg_b on the
     262,144-row channel, and the 3-D cg_a averaged over 17 iterations (the
     first one reads no previous direction)."""
-    assert bench.kernel_bytes("cg_b", **CH) * 262144 == 99614720
+    assert bench.kernel_bytes("cg_b", **CH) * 262144 == 98566144
     first = 1.0 / 17
     per_launch = bench.kernel_bytes("cg_a", first_frac=first, **D3) * 2097152
-    assert abs(per_launch - 1148252400) < 1.0
+    assert abs(per_launch - 1139863792) < 1.0
     # first iteration of cg_a: two population passes instead of three
-    assert bench.kernel_bytes("cg_a", first_frac=1.0, **CH) == 2 * 64 + 60
+    assert bench.kernel_bytes("cg_a", first_frac=1.0, **CH) == 2 * 64 + 56
 
 
 def test_fp64_plain_bytes():
     """FP64 plain: 8-byte values and populations, no references."""
     f64 = dict(Q=9, D=2, W=7, NB=5, s=8, sp=8, dev=False)
-    assert bench.kernel_bytes("cg_b", **f64) == 5 * 128 + 28 + 56 + 8
-    assert bench.kernel_bytes("stream", **f64) == 128 + 28 + 5 * 7 * 8 + 128
+    assert bench.kernel_bytes("cg_b", **f64) == 5 * 128 + 24 + 56 + 8
+    # plain populations: the diagonal coefficients are read
+    assert bench.kernel_bytes("stream", **f64) == 128 + 24 + 5 * 7 * 8 + 128
 
 
 @pytest.mark.parametrize("name,cls", [
