@@ -171,9 +171,9 @@ FEL_API fel_status fel_init_fields(fel_ctx* ctx, int inst, const fel_phys* phys,
 /* Advances every instance by n_steps time steps; asynchronous on the bound
  * stream.  The first call also settles whatever schedule the options left
  * to timing (fel_options.solver_batch, lds_staging, fused_reductions): it
- * launches the candidates on the solve's scratch buffers and synchronizes
- * the stream, so it must not be made while the caller captures that stream
- * into a graph.  The library captures the step into a graph of its own on
+ * launches the candidate kernels, then graphs of the whole mass solve, on
+ * the solve's scratch buffers and synchronizes the stream, so it must not
+ * be made while the caller captures that stream into a graph.  The library captures the step into a graph of its own on
  * the first call and replays it afterwards (on a non-default stream and
  * while not profiling). */
 FEL_API fel_status fel_step(fel_ctx* ctx, int n_steps);

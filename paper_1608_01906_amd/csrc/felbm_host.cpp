@@ -119,6 +119,7 @@ struct fel_ctx {
     int fused = 0;
     int fbatch[KC_COUNT] = {};
     bool fused_ok = false;
+    bool refined = false;  // schedule refined by timing whole solves (refine_schedule)
     std::vector<int32_t> fblocks;  // 4 ints per block
     int nfb = 0;
     // profiling
@@ -1034,6 +1035,25 @@ fel_status tune_fused_batches(fel_ctx* c) {
 // is then the whole gain).  Like the other tuning it touches only the
 // solve's scratch; the status word, which the final residual check may set
 // on that scratch, is restored afterwards.
+// Times the whole mass solve as a graph of the current schedule (kWarm
+// untimed and kReps timed replays).
+hipError_t time_solve(fel_ctx* c, hipEvent_t a, hipEvent_t b, float* ms) {
+    hipStream_t s = c->stream;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        e = enqueue_solve(c);
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = time_launches(c, a, b, [&] { return hipGraphLaunch(ge, s); }, ms);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
 fel_status choose_fused(fel_ctx* c) {
     if (!c->use_graph) {
         c->fused = 2;
@@ -1053,19 +1073,8 @@ fel_status choose_fused(fel_ctx* c) {
     float best_ms = 0.0f;
     for (int mode : {1, 2}) {
         c->fused = mode;
-        hipGraph_t g = nullptr;
-        hipGraphExec_t ge = nullptr;
-        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            e = enqueue_solve(c);
-            hipError_t e2 = hipStreamEndCapture(s, &g);
-            if (e == hipSuccess) e = e2;
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         float ms = 0.0f;
-        if (e == hipSuccess) e = time_launches(c, a, b, [&] { return hipGraphLaunch(ge, s); }, &ms);
-        if (ge) (void)hipGraphExecDestroy(ge);
-        if (g) (void)hipGraphDestroy(g);
+        hipError_t e = time_solve(c, a, b, &ms);
         if (e != hipSuccess) {
             st = fail(c, FEL_EDEVICE, "solve timing failed: %s", hipGetErrorString(e));
             break;
@@ -1077,6 +1086,67 @@ fel_status choose_fused(fel_ctx* c) {
     c->event_pool.push_back(a);
     c->event_pool.push_back(b);
     if (st != FEL_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipMemcpy(c->dev + c->off.status, &saved, 4, hipMemcpyHostToDevice));
+    return FEL_OK;
+}
+
+// Refines the schedule in context.  The first tuning times each kernel
+// alone, repeated on warm caches; here each solver class's allowed
+// schedules are timed as the whole mass solve (graph-replayed, the other
+// classes as chosen so far), one class at a time, and the fastest is kept.
+// Like the other tuning it touches only the solve's scratch, and the status
+// word is restored afterwards.
+fel_status refine_schedule(fel_ctx* c) {
+    if (!c->use_graph || c->opt.mass_mode == FEL_MASS_LUMPED) return FEL_OK;
+    const bool fused = c->fused == 2;
+    const int sb = c->opt.solver_batch, ls = c->opt.lds_staging;
+    if (sb && (fused || ls)) return FEL_OK;  // the options fix every choice
+    hipStream_t s = c->stream;
+    uint32_t saved = 0;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipMemcpy(&saved, c->dev + c->off.status, 4, hipMemcpyDeviceToHost));
+    hipEvent_t a = get_event(c), b = get_event(c);
+    if (!a || !b) return fail(c, FEL_EDEVICE, "event creation failed");
+    const bool profiling = c->profiling;  // no per-launch events inside a capture
+    c->profiling = false;
+    float cur = 0.0f;
+    hipError_t e = time_solve(c, a, b, &cur);
+    std::vector<int> classes;
+    if (c->opt.mass_mode == FEL_MASS_CHEBYSHEV) classes = {KC_CHEB};
+    else classes = {KC_CG_B, KC_CG_A, KC_CG_INIT};
+    for (int cls : classes) {
+        if (e != hipSuccess) break;
+        int* bt = fused ? &c->fbatch[cls] : &c->batch[cls];
+        int* sg = fused ? nullptr : &c->stage[cls];
+        const int keep_b = *bt, keep_s = sg ? *sg : 1;
+        int best_b = keep_b, best_s = keep_s;
+        float best = cur;
+        for (int st : {1, 2}) {
+            if (fused && st == 2) continue;  // the fused kernels gather directly
+            if (!fused && ls && st != ls) continue;
+            for (int t : {1, 2, 4}) {
+                if (sb && t != sb) continue;
+                if (fused && c->W != 7 && t != 1) continue;
+                if (st == 2 && !stage_fits(c, t)) continue;
+                if (t == keep_b && st == keep_s) continue;
+                *bt = t;
+                if (sg) *sg = st;
+                float ms = 0.0f;
+                e = time_solve(c, a, b, &ms);
+                if (e != hipSuccess) break;
+                if (ms < best) best = ms, best_b = t, best_s = st;
+            }
+            if (e != hipSuccess) break;
+        }
+        *bt = best_b;
+        if (sg) *sg = best_s;
+        cur = best;
+    }
+    c->profiling = profiling;
+    c->event_pool.push_back(a);
+    c->event_pool.push_back(b);
+    if (e != hipSuccess) return fail(c, FEL_EDEVICE, "solve timing failed: %s", hipGetErrorString(e));
     HIP_TRY(c, hipStreamSynchronize(s));
     HIP_TRY(c, hipMemcpy(c->dev + c->off.status, &saved, 4, hipMemcpyHostToDevice));
     return FEL_OK;
@@ -1201,6 +1271,11 @@ fel_status fel_step(fel_ctx* c, int n_steps) {
             if (st == FEL_OK && c->fused == 0) st = choose_fused(c);
             if (st != FEL_OK) return st;
         }
+    }
+    if (!c->refined) {
+        fel_status st = refine_schedule(c);
+        if (st != FEL_OK) return st;
+        c->refined = true;
     }
     if (c->profiling || !c->use_graph) {
         // profiling launches directly: each kernel's events are stamped by its own dispatch
