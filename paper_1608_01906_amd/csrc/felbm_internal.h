@@ -1,5 +1,5 @@
 // Private layout shared by the host side (felbm_host.cpp) and the kernels
-// (felbm_kernels.hip).  Not part of the C ABI.
+// (felbm_kernels.hip, felbm_solver.hip).  Not part of the C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -5,7 +5,11 @@
 //                                 preconditioner z = r / m, x0 = rhs / m
 //   k_finalize                    per-instance totals of the tile partials
 //                                 -> CG scalars (fixed summation order)
+//   k_cg_*_fused, k_fused_check   the same CG with the scalars formed by
+//                                 every block of the next launch (2-D)
 //   k_cheb_first / k_cheb         Chebyshev semi-iteration, no reductions
+//   *_lds                         LDS-staged forms of the above (neighbour
+//                                 values read from a per-tile stage)
 //   k_lumped                      lumped-mass shortcut Delta = rhs / m
 //
 // Every launch covers the NP = 2(Q - 1) moving populations of all
