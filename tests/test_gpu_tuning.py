@@ -87,6 +87,30 @@ def test_tuning_reads_zero_before_first_step(felbm):
     assert all(t[k][0] in (1, 2, 4) and t[k][1] in (1, 2) for k in ("cg_init", "cg_a", "cg_b"))
 
 
+@pytest.mark.parametrize("mass_mode", [0, 2])
+def test_partly_fixed_schedules_are_kept(felbm, mass_mode):
+    """Options that fix part of the schedule hold through the whole tuning,
+    the in-context pass that times whole solves included: a fixed staging
+    leaves only batches to choose, a fixed batch only the staging (finalize
+    launches forced, so the choice applies to the kernels that run)."""
+    w = _workload(2)
+    classes = ("cg_init", "cg_a", "cg_b") if mass_mode == 0 else ("cheb",)
+    for sg in (1, 2):
+        ctx = felbm.from_workload(w, precision="fp32", mass_mode=mass_mode, lds_staging=sg, fused_reductions=1)
+        ctx.step(1)
+        ctx.sync()
+        t = ctx.tuning()
+        print("staging fixed", sg, t, flush=True)
+        assert all(t[k][1] == sg and t[k][0] in (1, 2, 4) for k in classes)
+    for b in (1, 2, 4):
+        ctx = felbm.from_workload(w, precision="fp32", mass_mode=mass_mode, solver_batch=b, fused_reductions=1)
+        ctx.step(1)
+        ctx.sync()
+        t = ctx.tuning()
+        print("batch fixed", b, t, flush=True)
+        assert all(t[k][0] == b and t[k][1] in (1, 2) for k in classes)
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
 def test_fused_reductions_vs_oracle(felbm, oracle_mod, precision, tol):
     """The fused-reduction CG (no finalize launches) against the oracle, on
