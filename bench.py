@@ -54,9 +54,16 @@ def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, 
         return NP * sp + ref + pat + NB * (W - 1 if dev else W) * s + NP * s
     if cls == "cg_init":
         return 3 * NP * s + pat + W * s + s
+    qrec = W >= 15  # the CG carries q = M p by its own recurrence on the 3-D widths
     if cls == "cg_a":
+        if qrec:  # read r, p, q; write p, q (the first iteration reads r only)
+            return (5 - 2 * first_frac) * NP * s + pat + W * s + s
+        # read r, p_old; write p_new (p_old unread on the first iteration)
         return (3 - first_frac) * NP * s + pat + W * s + s
     if cls == "cg_b":
+        if qrec:  # read p, q, x, r; write x, r (own rows only)
+            return 6 * NP * s + s
+        # read p, x, r; write x, r (M p formed again from neighbour values of p)
         return 5 * NP * s + pat + W * s + s
     if cls == "cheb_first":
         return 3 * NP * s + pat + W * s + s

@@ -105,6 +105,8 @@ typedef struct {
     int lds_staging;      /* mass-solve kernels read neighbour values 1 = by direct gathers from
                              memory, 2 = from a per-tile stage in LDS (the tile's rows and its halo
                              loaded once per population, coalesced), 0 = chosen per kernel by timing.
+                             On 3-D layouts (ELL width 15 and up) the CG carries M p by its own
+                             recurrence: its second kernel reads no neighbour values and runs direct.
                              Staging needs tile halos of at most 1024 rows and two stages of the
                              population batch within 60 KB of LDS; a forced 2 that does not fit makes
                              the first fel_step return FEL_EINVAL (0 then keeps direct gathers).

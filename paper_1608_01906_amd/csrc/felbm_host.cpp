@@ -580,6 +580,7 @@ static fel_status plan_layout(fel_ctx* c) {
     for (int i = 0; i < n; i++) wmax = std::max(wmax, c->inst[i].mesh.W);
     c->W = supported_width(c->opt.lattice, wmax);
     if (c->W < 0) return fail(c, FEL_EINVAL, "mesh valence %d above the supported ELL width", wmax);
+    if (c->W >= kQRecurrenceWidth) c->stage[KC_CG_B] = 1;  // recurrence form: cg_b has no staged form
     int64_t rows = 0;
     c->tile_inst.clear();
     for (int i = 0; i < n; i++) {
@@ -1122,9 +1123,11 @@ fel_status refine_schedule(fel_ctx* c) {
         const int keep_b = *bt, keep_s = sg ? *sg : 1;
         int best_b = keep_b, best_s = keep_s;
         float best = cur;
+        // the recurrence form's cg_b has no staged form
+        const int fixed_st = (cls == KC_CG_B && c->W >= kQRecurrenceWidth) ? 1 : ls;
         for (int st : {1, 2}) {
             if (fused && st == 2) continue;  // the fused kernels gather directly
-            if (!fused && ls && st != ls) continue;
+            if (!fused && fixed_st && st != fixed_st) continue;
             for (int t : {1, 2, 4}) {
                 if (sb && t != sb) continue;
                 if (fused && c->W != 7 && t != 1) continue;

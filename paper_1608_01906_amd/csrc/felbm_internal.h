@@ -54,8 +54,8 @@ struct DevLayout {
     // CG work vectors over the 2(Q-1) moving populations, T [2(Q-1)][R]
     void* X;
     void* Rv;
-    void* Pa;
-    void* Pb;
+    void* Pa;              // CG recompute form: p alternates between Pa and Pb;
+    void* Pb;              // recurrence form: p in Pa, q = M p in Pb (rhs until cg_init)
     // nodal fields, T
     void* rho;             // [R]
     void* grad;            // [dim][R]
@@ -129,6 +129,10 @@ hipError_t launch_cg_init_fused(const DevLayout& L, int batch, hipStream_t s);
 hipError_t launch_cg_a_fused(const DevLayout& L, int it, int batch, hipStream_t s);
 hipError_t launch_cg_b_fused(const DevLayout& L, int it, int batch, hipStream_t s);
 hipError_t launch_fused_check(const DevLayout& L, hipStream_t s);
+// ELL widths from which the CG carries q = M p by its own recurrence (the
+// 3-D layouts, where neighbour gathers dominate): the second CG kernel then
+// reads own rows only and has no staged form.
+constexpr int kQRecurrenceWidth = 15;
 constexpr int kHaloRounds = 4;       // LDS staging: halo entries per thread at most (halo <= 4 TILE)
 constexpr int kStageBytes = 60 * 1024;  // LDS staging: dynamic LDS per block at most (2 batches of sw rows)
 constexpr int kFusedTiles = 4;       // tiles per fused-reduction block

@@ -265,6 +265,86 @@ struct CgBRows {
     }
 };
 
+// Two forms of the CG iteration.  The recompute form above keeps three
+// vectors per population in the passes (r, p and x; M p formed twice from
+// neighbour values of p) and gathers r and p in cg_a and p in cg_b.  On the
+// 3-D layouts (ELL width 15 and up) gathers dominate, so there q = M p is
+// kept as a fourth vector with its own recurrence q = M z + beta q, which
+// is M p in exact arithmetic: cg_a gathers only r, cg_b reads own rows
+// only.  p lives in Pa and q in Pb (the right-hand side until cg_init has
+// read it), both updated in place.
+template <int W>
+constexpr bool q_recurrence() { return W >= kQRecurrenceWidth; }
+
+// cg_a, recurrence form: z = r / m, p = z + beta p, q = M z + beta q (p, q
+// of the previous iteration unread on the first); reduces p.q -> alpha.
+template <typename T, int W, bool FIRST>
+struct CgAQRows {
+    static constexpr bool kDots = true;
+    struct Regs { T g[W]; T own, p, q; };
+    RowOps<T, W, true> o;
+    const T* Rv;
+    T *P, *Qv;
+    const double* beta;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
+        const T* rv = Rv + (int64_t)j * R;
+        r.own = rv[row];
+        r.g[0] = r.own;
+#pragma unroll
+        for (int k = 1; k < W; k++) r.g[k] = gat(rv, o.c[k]);
+        if constexpr (!FIRST) {
+            const int64_t i = (int64_t)j * R + row;
+            r.p = P[i];
+            r.q = Qv[i];
+        }
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k]);
+        T pn = r.own * o.mrow, qn = acc;
+        if constexpr (!FIRST) {
+            const T bet = (T)beta[j];
+            pn += bet * r.p;
+            qn += bet * r.q;
+        }
+        const int64_t i = (int64_t)j * R + row;
+        P[i] = pn;
+        Qv[i] = qn;
+        return (double)pn * (double)qn;
+    }
+};
+
+// cg_b, recurrence form: x += alpha p, r -= alpha q; reduces r.z -> beta.
+template <typename T>
+struct CgBQRows {
+    static constexpr bool kDots = true;
+    struct Regs { T p, q, x, r; };
+    const T *P, *Qv;
+    T *X, *Rv;
+    const double* alpha;
+    T mrow;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ void load(int j, Regs& r) const {
+        const int64_t i = (int64_t)j * R + row;
+        r.p = P[i];
+        r.q = Qv[i];
+        r.x = X[i];
+        r.r = Rv[i];
+    }
+    __device__ __forceinline__ double use(int j, const Regs& r) const {
+        const T al = (T)alpha[j];
+        const T res = r.r - al * r.q;
+        const int64_t i = (int64_t)j * R + row;
+        X[i] = r.x + al * r.p;
+        Rv[i] = res;
+        return (double)res * (double)res * (double)mrow;
+    }
+};
+
 template <typename T>
 __device__ __forceinline__ T* vec(void* base) {
     return reinterpret_cast<T*>(base);
@@ -294,7 +374,20 @@ __global__ __launch_bounds__(TILE) void k_cg_a(DevLayout L, int tile_begin, int 
     T* Pnew = vec<T>(flip ? L.Pb : L.Pa);
     const double* beta = L.beta + inst * NP;
     FEL_REDUCER(red, NP);
-    if (first) {
+    if constexpr (q_recurrence<W>()) {
+        auto go = [&](auto& b) {
+            b.o.load(L, R, row);
+            b.Rv = Rv, b.P = vec<T>(L.Pa), b.Qv = vec<T>(L.Pb), b.beta = beta, b.R = R, b.row = row;
+            run_rows<NP, CH>(b, &red);
+        };
+        if (first) {
+            CgAQRows<T, W, true> b;
+            go(b);
+        } else {
+            CgAQRows<T, W, false> b;
+            go(b);
+        }
+    } else if (first) {
         CgARows<T, W, true> b;
         b.o.load(L, R, row);
         b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.beta = beta, b.R = R, b.row = row;
@@ -312,16 +405,29 @@ template <typename T, int W, int NP, int CH>
 __global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int flip) {
     FEL_ROW_LAYOUT();
     const int inst = L.tile_inst[tile];
-    CgBRows<T, W> b;
-    b.o.load(L, R, row);
-    b.Pn = vec<T>(flip ? L.Pb : L.Pa);
-    b.X = vec<T>(L.X);
-    b.Rv = vec<T>(L.Rv);
-    b.alpha = L.alpha + inst * NP;
-    b.R = R;
-    b.row = row;
     FEL_REDUCER(red, NP);
-    run_rows<NP, CH>(b, &red);
+    if constexpr (q_recurrence<W>()) {
+        CgBQRows<T> b;
+        b.P = vec<T>(L.Pa);
+        b.Qv = vec<T>(L.Pb);
+        b.X = vec<T>(L.X);
+        b.Rv = vec<T>(L.Rv);
+        b.alpha = L.alpha + inst * NP;
+        b.mrow = ld<T>(L.minv, row);
+        b.R = R;
+        b.row = row;
+        run_rows<NP, CH>(b, &red);
+    } else {
+        CgBRows<T, W> b;
+        b.o.load(L, R, row);
+        b.Pn = vec<T>(flip ? L.Pb : L.Pa);
+        b.X = vec<T>(L.X);
+        b.Rv = vec<T>(L.Rv);
+        b.alpha = L.alpha + inst * NP;
+        b.R = R;
+        b.row = row;
+        run_rows<NP, CH>(b, &red);
+    }
     red.finish(L, tile);
 }
 
@@ -743,6 +849,43 @@ struct CgAStaged {
     }
 };
 
+// cg_a staged, recurrence form: stage z = r / m; p = z + beta p and
+// q = M z + beta q in place.  (The recurrence form's cg_b reads no
+// neighbour values and has no staged form.)
+template <typename T, int W, bool FIRST>
+struct CgAQStaged {
+    static constexpr bool kDots = true;
+    struct Own { T p, q; };
+    LocalCols<W> l;
+    T mv[W];
+    const T *Rv, *minv;
+    T *P, *Qv;
+    const double* beta;
+    int64_t R;
+    int row;
+    __device__ __forceinline__ T pre(int g) const { return minv[g]; }
+    __device__ __forceinline__ T stage(int j, int g, T mg) const { return Rv[(int64_t)j * R + g] * mg; }
+    __device__ __forceinline__ void keep(int j, Own& o) const {
+        if constexpr (!FIRST) {
+            const int64_t i = (int64_t)j * R + row;
+            o.p = P[i];
+            o.q = Qv[i];
+        }
+    }
+    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
+        T pn = st[threadIdx.x], qn = lds_row_product<T, W>(mv, l, st);
+        if constexpr (!FIRST) {
+            const T bet = (T)beta[j];
+            pn += bet * o.p;
+            qn += bet * o.q;
+        }
+        const int64_t i = (int64_t)j * R + row;
+        P[i] = pn;
+        Qv[i] = qn;
+        return (double)pn * (double)qn;
+    }
+};
+
 // cg_b staged: stage p
 template <typename T, int W>
 struct CgBStaged {
@@ -865,7 +1008,25 @@ __global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, 
         b.Pnew = vec<T>(flip ? L.Pb : L.Pa);
         b.beta = L.beta + inst * NP;
     };
-    if (first) {
+    auto setup_q = [&](auto& b) {
+        staged_row_setup<T, W>(b, L, R, row);
+        b.minv = reinterpret_cast<const T*>(L.minv);
+        b.Rv = vec<T>(L.Rv);
+        b.P = vec<T>(L.Pa);
+        b.Qv = vec<T>(L.Pb);
+        b.beta = L.beta + inst * NP;
+    };
+    if constexpr (q_recurrence<W>()) {
+        if (first) {
+            CgAQStaged<T, W, true> b;
+            setup_q(b);
+            run_staged<T, NP, CH>(b, L, tile, row, sh, &red);
+        } else {
+            CgAQStaged<T, W, false> b;
+            setup_q(b);
+            run_staged<T, NP, CH>(b, L, tile, row, sh, &red);
+        }
+    } else if (first) {
         CgAStaged<T, W, true> b;
         setup(b);
         run_staged<T, NP, CH>(b, L, tile, row, sh, &red);
@@ -882,15 +1043,30 @@ __global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, 
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
     const int inst = L.tile_inst[tile];
-    CgBStaged<T, W> b;
-    staged_row_setup<T, W>(b, L, R, row);
-    b.mrow = ld<T>(L.minv, row);
-    b.Pn = vec<T>(flip ? L.Pb : L.Pa);
-    b.X = vec<T>(L.X);
-    b.Rv = vec<T>(L.Rv);
-    b.alpha = L.alpha + inst * NP;
     FEL_REDUCER(red, NP);
-    run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
+    if constexpr (q_recurrence<W>()) {
+        // nothing to stage in the recurrence form (the host never selects
+        // this kernel there); the direct rows keep it well defined
+        CgBQRows<T> b;
+        b.P = vec<T>(L.Pa);
+        b.Qv = vec<T>(L.Pb);
+        b.X = vec<T>(L.X);
+        b.Rv = vec<T>(L.Rv);
+        b.alpha = L.alpha + inst * NP;
+        b.mrow = ld<T>(L.minv, row);
+        b.R = R;
+        b.row = row;
+        run_rows<NP, CH>(b, &red);
+    } else {
+        CgBStaged<T, W> b;
+        staged_row_setup<T, W>(b, L, R, row);
+        b.mrow = ld<T>(L.minv, row);
+        b.Pn = vec<T>(flip ? L.Pb : L.Pa);
+        b.X = vec<T>(L.X);
+        b.Rv = vec<T>(L.Rv);
+        b.alpha = L.alpha + inst * NP;
+        run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
+    }
     red.finish(L, tile);
 }
 

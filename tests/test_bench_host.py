@@ -49,10 +49,13 @@ def test_bytes_per_launch_match_the_reported_figures():
     262,144-row channel, and the 3-D cg_a averaged over 17 iterations (the
     first one reads no previous direction)."""
     assert bench.kernel_bytes("cg_b", **CH) * 262144 == 98566144
+    # 3-D (recurrence form): cg_a reads r p q and writes p q, the first of
+    # 17 iterations reads r only; cg_b streams p q x r, writes x r
     first = 1.0 / 17
     per_launch = bench.kernel_bytes("cg_a", first_frac=first, **D3) * 2097152
-    assert abs(per_launch - 1139863792) < 1.0
-    # first iteration of cg_a: two population passes instead of three
+    assert abs(per_launch - ((5 - 2 / 17) * 144 + 56 + 60 + 4) * 2097152) < 1.0
+    assert bench.kernel_bytes("cg_b", **D3) == 6 * 144 + 4
+    # first iteration of cg_a in 2-D: two population passes instead of three
     assert bench.kernel_bytes("cg_a", first_frac=1.0, **CH) == 2 * 64 + 56
 
 

@@ -56,7 +56,8 @@ def test_solver_schedules(felbm, oracle_mod, dim, precision, mass_mode, node_ord
             ctx.sync()
             states[sg, nb] = ctx.get_state(0)
             t = ctx.tuning()
-            assert all(t[name] == (nb, sg) for name in SOLVER)
+            # on 3-D layouts the second CG kernel reads no neighbour values: never staged
+            assert all(t[name] == (nb, 1 if (name == "cg_b" and dim == 3) else sg) for name in SOLVER)
             e = compare_fields(ctx.read_fields(0), o.fields(), inst)
             for k in ("rho", "u", "C"):
                 assert e[k] < tol, (sg, nb, k, e[k])
