@@ -38,14 +38,15 @@ DESCRIPTIONS = {
 
 
 def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, dev: bool,
-                 first_frac: float = 0.0) -> float:
+                 first_frac: float = 0.0, K: int = 0) -> float:
     """Algorithmic HBM bytes per node row of one launch of a kernel class:
     every operand read or written once (gathers of neighbour values served
     by cache), pattern = 4-byte column index per off-diagonal slot (slot 0
     is the row itself).  s = operator/vector value size, sp = stored
     population size, dev = deviation storage with two 4-byte node
     references, where streaming works on differences to the row's own value
-    and needs no diagonal coefficients."""
+    and needs no diagonal coefficients.  K = CG iterations (every
+    iteration's direction is stored and x formed once, by cg_x)."""
     NP = 2 * (Q - 1)
     P = 2 * Q
     pat = (W - 1) * 4
@@ -61,10 +62,13 @@ def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, 
         # read r, p_old; write p_new (p_old unread on the first iteration)
         return (3 - first_frac) * NP * s + pat + W * s + s
     if cls == "cg_b":
-        if qrec:  # read p, q, x, r; write x, r (own rows only)
-            return 6 * NP * s + s
-        # read p, x, r; write x, r (M p formed again from neighbour values of p)
-        return 5 * NP * s + pat + W * s + s
+        if qrec:  # read q, r; write r (own rows only)
+            return 3 * NP * s + s
+        # read p, r; write r (M p formed again from neighbour values of p)
+        return 3 * NP * s + pat + W * s + s
+    if cls == "cg_x":
+        # x = x_0 + sum_k alpha_k p_k: read x and the K directions, write x
+        return (2 + K) * NP * s
     if cls == "cheb_first":
         return 3 * NP * s + pat + W * s + s
     if cls == "cheb":
@@ -157,7 +161,7 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="chan
             continue
         first = (1.0 / info["cg_iters"]) if name == "cg_a" and info["cg_iters"] else 0.0
         b = kernel_bytes(name, Q=w.lattice, D=D, W=info["ell_width"], NB=NB, s=s, sp=sp,
-                         dev=precision != "fp64", first_frac=first) * N
+                         dev=precision != "fp64", first_frac=first, K=info["cg_iters"]) * N
         if name == "cheb":
             # one first launch (gathers rhs, writes x0 and x1) per K launches
             K = info["cg_iters"]

@@ -103,7 +103,7 @@ struct fel_ctx {
     int hmax = 0, sw = 0;
     int64_t halo_total = 0;
     struct Off {
-        size_t lcol, halo_ptr, halo_col, fblocks, fpart0, fpart1, srz, col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, rho, grad,
+        size_t lcol, halo_ptr, halo_col, fblocks, fpart0, fpart1, srz, col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, Ph, rho, grad,
             mu, S, u, p, partial, rz, rz0, alpha, beta, sums, status, end;
     } off{};
     // graph
@@ -629,6 +629,9 @@ static fel_status plan_layout(fel_ctx* c) {
     f.Rv = take(s * NP * R);
     f.Pa = take(s * NP * R);
     f.Pb = take(s * NP * R);
+    // the consistent-mass CG keeps every iteration's search direction
+    const size_t K = c->opt.mass_mode == FEL_MASS_CONSISTENT ? (size_t)c->cg_iters : 0;
+    f.Ph = take(s * NP * R * K);
     f.rho = take(s * R);
     f.grad = take(s * D * R);
     f.mu = take(s * R);
@@ -638,7 +641,7 @@ static fel_status plan_layout(fel_ctx* c) {
     f.partial = take(8 * (size_t)c->ntiles * std::max(NP, 8));
     f.rz = take(8 * (size_t)n * NP);
     f.rz0 = take(8 * (size_t)n * NP);
-    f.alpha = take(8 * (size_t)n * NP);
+    f.alpha = take(8 * std::max<size_t>(K, 1) * n * NP);
     f.beta = take(8 * (size_t)n * NP);
     f.sums = take(8 * 8 * (size_t)n);
     f.fblocks = take(16 * (size_t)std::max(c->nfb, 1));
@@ -750,6 +753,8 @@ static void set_pointers(fel_ctx* c) {
     L.Rv = d + f.Rv;
     L.Pa = d + f.Pa;
     L.Pb = d + f.Pb;
+    L.Ph = d + f.Ph;
+    L.K = c->opt.mass_mode == FEL_MASS_CONSISTENT ? c->cg_iters : 0;
     L.rho = d + f.rho;
     L.grad = d + f.grad;
     L.mu = d + f.mu;
@@ -881,49 +886,53 @@ hipError_t enqueue_solve(fel_ctx* c) {
                 hipSuccess)
                 return e;
         }
-        return timed(c, KC_FINALIZE, [&] { return launch_fused_check(L, s); });
+        if ((e = timed(c, KC_FINALIZE, [&] { return launch_fused_check(L, s); })) != hipSuccess) return e;
+        return timed(c, KC_CG_X, [&] { return launch_cg_x(L, tb, nt, s); });
     }
     const int ni = c->ninst, np = c->NP;
-    auto fin = [&](int op) { return timed(c, KC_FINALIZE, [&] { return launch_finalize(L, 0, ni, op, np, s); }); };
+    auto fin = [&](int op, int it = 0) {
+        return timed(c, KC_FINALIZE, [&] { return launch_finalize(L, 0, ni, op, np, s, it); });
+    };
     if ((e = timed(c, KC_CG_INIT, [&] {
              return launch_cg_init(L, tb, nt, c->batch[KC_CG_INIT], staged(c, KC_CG_INIT), s);
          })) != hipSuccess)
         return e;
     if ((e = fin(0)) != hipSuccess) return e;
     for (int it = 0; it < c->cg_iters; it++) {
-        const bool flip = (it & 1) != 0;
         if ((e = timed(c, KC_CG_A, [&] {
-                 return launch_cg_a(L, tb, nt, it == 0, flip, c->batch[KC_CG_A], staged(c, KC_CG_A), s);
+                 return launch_cg_a(L, tb, nt, it == 0, it, c->batch[KC_CG_A], staged(c, KC_CG_A), s);
              })) != hipSuccess)
             return e;
-        if ((e = fin(1)) != hipSuccess) return e;
+        if ((e = fin(1, it)) != hipSuccess) return e;
         if ((e = timed(c, KC_CG_B, [&] {
-                 return launch_cg_b(L, tb, nt, flip, c->batch[KC_CG_B], staged(c, KC_CG_B), s);
+                 return launch_cg_b(L, tb, nt, it, c->batch[KC_CG_B], staged(c, KC_CG_B), s);
              })) != hipSuccess)
             return e;
         if ((e = fin(it == c->cg_iters - 1 ? 3 : 2)) != hipSuccess) return e;
     }
-    return hipSuccess;
+    return timed(c, KC_CG_X, [&] { return launch_cg_x(L, tb, nt, s); });
 }
 
 // Chooses the schedule of each solver kernel left to the tuner: the
 // population batch (1, 2 or 4: how many populations' loads its pipeline
 // issues ahead, or stages per LDS pass) and direct gathers vs LDS staging,
 // by timing every allowed candidate on the bound layout.  The launches only
-// touch the solve's scratch vectors (X, Rv, Pa, Pb, tile partials), which
-// the next step's streaming and first solver launch rewrite before reading.
+// touch the solve's scratch (X, Rv, Pa, Pb, the stored directions, the
+// alpha history, tile partials), which the next solve rewrites before
+// reading.
 fel_status tune_schedule(fel_ctx* c) {
     const DevLayout& L = c->L;
     hipStream_t s = c->stream;
     const int nt = c->ntiles;
+    const int tit = L.K > 1 ? 1 : 0;  // a CG iteration to time (the second, if there is one)
     const double gamma = 2.0 / (1.0 + 1.0 / (c->lat.D + 2));
     hipEvent_t a = get_event(c), b = get_event(c);
     if (!a || !b) return fail(c, FEL_EDEVICE, "event creation failed");
     auto run = [&](int cls, int t, bool st) -> hipError_t {
         switch (cls) {
             case KC_CG_INIT: return launch_cg_init(L, 0, nt, t, st, s);
-            case KC_CG_A: return launch_cg_a(L, 0, nt, false, false, t, st, s);
-            case KC_CG_B: return launch_cg_b(L, 0, nt, false, t, st, s);
+            case KC_CG_A: return launch_cg_a(L, 0, nt, tit == 0, tit, t, st, s);
+            case KC_CG_B: return launch_cg_b(L, 0, nt, tit, t, st, s);
             default: return launch_cheb(L, 0, nt, 1, 1.0, gamma, t, st, s);
         }
     };
@@ -998,6 +1007,7 @@ hipError_t time_launches(fel_ctx* c, hipEvent_t a, hipEvent_t b, F&& run, float*
 fel_status tune_fused_batches(fel_ctx* c) {
     const DevLayout& L = c->L;
     hipStream_t s = c->stream;
+    const int tit = L.K > 1 ? 1 : 0;
     if (c->opt.solver_batch) {
         for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B}) c->fbatch[cls] = c->W == 7 ? c->opt.solver_batch : 1;
         return FEL_OK;
@@ -1013,8 +1023,8 @@ fel_status tune_fused_batches(fel_ctx* c) {
             float ms = 0.0f;
             hipError_t e = time_launches(c, a, b, [&] {
                 return cls == KC_CG_INIT ? launch_cg_init_fused(L, t, s)
-                       : cls == KC_CG_A  ? launch_cg_a_fused(L, 1, t, s)
-                                         : launch_cg_b_fused(L, 1, t, s);
+                       : cls == KC_CG_A  ? launch_cg_a_fused(L, tit, t, s)
+                                         : launch_cg_b_fused(L, tit, t, s);
             }, &ms);
             if (e != hipSuccess) {
                 st = fail(c, FEL_EDEVICE, "fused tuning launch failed: %s", hipGetErrorString(e));

@@ -54,8 +54,12 @@ struct DevLayout {
     // CG work vectors over the 2(Q-1) moving populations, T [2(Q-1)][R]
     void* X;
     void* Rv;
-    void* Pa;              // CG recompute form: p alternates between Pa and Pb;
-    void* Pb;              // recurrence form: p in Pa, q = M p in Pb (rhs until cg_init)
+    void* Pa;              // Chebyshev: an iterate; CG recurrence form: q = M p
+    void* Pb;              // right-hand side of the solve
+    // CG search directions of every iteration, T [K][2(Q-1)][R]: x is
+    // formed once after the last iteration as x_0 + sum_k alpha_k p_k
+    void* Ph;
+    int K;                 // CG iterations per solve
     // nodal fields, T
     void* rho;             // [R]
     void* grad;            // [dim][R]
@@ -67,7 +71,7 @@ struct DevLayout {
     double* partial;       // [2(Q-1)][ntiles] tile partials (also reused for the conserved sums)
     double* rz;            // [ninst][2(Q-1)]
     double* rz0;           // [ninst][2(Q-1)]
-    double* alpha;         // [ninst][2(Q-1)]
+    double* alpha;         // [K][ninst][2(Q-1)] (one slice per CG iteration)
     double* beta;          // [ninst][2(Q-1)]
     double* sums;          // [ninst][8]
     uint32_t* status;      // [1] bit 0 non-finite, bit 1 CG residual above tolerance
@@ -98,6 +102,7 @@ enum KernelClass {
     KC_SUMS,
     KC_FINALIZE,
     KC_CHEB,
+    KC_CG_X,
     KC_COUNT
 };
 
@@ -115,13 +120,18 @@ hipError_t launch_stream(const DevLayout& L, int tile_begin, int ntiles, hipStre
 // The solver launchers take the population batch (1, 2 or 4) of their
 // pipeline or LDS pass and run the LDS-staged kernel when `staged`.
 hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, int batch, bool staged, hipStream_t s);
-hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, bool flip, int batch, bool staged,
+// it = CG iteration: p_it is written to (cg_a) and read from (cg_b) slice
+// it of Ph, alpha_it to slice it of alpha.
+hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, int it, int batch, bool staged,
                        hipStream_t s);
-hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, bool flip, int batch, bool staged,
+hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, int it, int batch, bool staged,
                        hipStream_t s);
+// x += sum over the K iterations of alpha_k p_k, in iteration order
+hipError_t launch_cg_x(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 // op: 0 CG init, 1 alpha, 2 beta, 3 final residual check, 4 conserved sums;
 // nvals values per tile (partials stored population-major)
-hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int nvals, hipStream_t s);
+hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int nvals, hipStream_t s,
+                           int it = 0);
 hipError_t launch_lumped(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 // Fused-reduction CG (2-D, no finalize launches): every block sums the
 // previous launch's block partials of its instance itself.  it = iteration.

@@ -19,8 +19,8 @@ namespace fel {
 thread_local LaunchEvents g_launch_events;
 
 const char* kernel_class_name(int k) {
-    static const char* names[KC_COUNT] = {"stream", "cg_init", "cg_a", "cg_b", "lumped", "moments",
-                                          "grad", "div", "collide", "init", "sums", "finalize", "cheb"};
+    static const char* names[KC_COUNT] = {"stream", "cg_init", "cg_a", "cg_b", "lumped", "moments", "grad",
+                                          "div", "collide", "init", "sums", "finalize", "cheb", "cg_x"};
     return (k >= 0 && k < KC_COUNT) ? names[k] : "?";
 }
 

@@ -33,7 +33,7 @@ enum FinOp { FIN_CG_INIT = 0, FIN_CG_A, FIN_CG_B, FIN_CG_LAST, FIN_SUMS };
 constexpr int FIN_THREADS = 1024;
 
 template <int NP>
-__global__ __launch_bounds__(FIN_THREADS) void k_finalize(DevLayout L, int inst_begin, int op) {
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(DevLayout L, int inst_begin, int op, int it) {
     __shared__ double fin[FIN_THREADS / 64];
     const int inst = inst_begin + blockIdx.x;
     const int j = blockIdx.y;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(DevLayout L, int inst_
         L.beta[i] = 0.0;
         break;
     case FIN_CG_A:
-        L.alpha[i] = (tot != 0.0) ? L.rz[i] / tot : 0.0;
+        L.alpha[(int64_t)it * L.ninst * NP + i] = (tot != 0.0) ? L.rz[i] / tot : 0.0;
         break;
     case FIN_CG_B: {
         const double rz = L.rz[i];
@@ -229,14 +229,15 @@ struct CgARows {
     }
 };
 
-// cg_b: x += alpha p, r -= alpha M p (M p recomputed), reduces r.z -> beta
+// cg_b: r -= alpha M p (M p recomputed), reduces r.z -> beta (x is formed
+// after the last iteration from the stored directions)
 template <typename T, int W>
 struct CgBRows {
     static constexpr bool kDots = true;
-    struct Regs { T g[W]; T own, x, r; };
+    struct Regs { T g[W]; T own, r; };
     RowOps<T, W, false> o;
     const T* Pn;
-    T *X, *Rv;
+    T* Rv;
     const double* alpha;
     int64_t R;
     int row;
@@ -247,9 +248,7 @@ struct CgBRows {
         r.g[0] = r.own;
 #pragma unroll
         for (int k = 1; k < W; k++) r.g[k] = gat(p, o.c[k]);
-        const int64_t i = (int64_t)j * R + row;
-        r.x = X[i];
-        r.r = Rv[i];
+        r.r = Rv[(int64_t)j * R + row];
     }
     __device__ __forceinline__ double use(int j, const Regs& r) const {
         T qq = 0;
@@ -259,20 +258,19 @@ struct CgBRows {
         const int64_t i = (int64_t)j * R + row;
         const T res = r.r - al * qq;
         if (!live) return 0.0;
-        X[i] = r.x + al * r.own;
         Rv[i] = res;
         return (double)res * (double)res * (double)o.mrow;
     }
 };
 
-// Two forms of the CG iteration.  The recompute form above keeps three
-// vectors per population in the passes (r, p and x; M p formed twice from
-// neighbour values of p) and gathers r and p in cg_a and p in cg_b.  On the
-// 3-D layouts (ELL width 15 and up) gathers dominate, so there q = M p is
-// kept as a fourth vector with its own recurrence q = M z + beta q, which
-// is M p in exact arithmetic: cg_a gathers only r, cg_b reads own rows
-// only.  p lives in Pa and q in Pb (the right-hand side until cg_init has
-// read it), both updated in place.
+// Two forms of the CG iteration.  Both store every iteration's search
+// direction p_k (slice k of Ph) and form x once after the last iteration
+// (k_cg_x), so the iterations themselves never touch x.  The recompute
+// form above forms M p twice from neighbour values of p: cg_a gathers r and
+// p_{k-1}, cg_b gathers p_k.  On the 3-D layouts (ELL width 15 and up)
+// gathers dominate, so there q = M p is kept as a vector of its own (in Pa)
+// with the recurrence q = M z + beta q, which is M p in exact arithmetic:
+// cg_a gathers only r, cg_b reads own rows only (q and r).
 template <int W>
 constexpr bool q_recurrence() { return W >= kQRecurrenceWidth; }
 
@@ -283,8 +281,8 @@ struct CgAQRows {
     static constexpr bool kDots = true;
     struct Regs { T g[W]; T own, p, q; };
     RowOps<T, W, true> o;
-    const T* Rv;
-    T *P, *Qv;
+    const T *Rv, *Pold;
+    T *Pnew, *Qv;
     const double* beta;
     int64_t R;
     int row;
@@ -296,7 +294,7 @@ struct CgAQRows {
         for (int k = 1; k < W; k++) r.g[k] = gat(rv, o.c[k]);
         if constexpr (!FIRST) {
             const int64_t i = (int64_t)j * R + row;
-            r.p = P[i];
+            r.p = Pold[i];
             r.q = Qv[i];
         }
     }
@@ -311,35 +309,32 @@ struct CgAQRows {
             qn += bet * r.q;
         }
         const int64_t i = (int64_t)j * R + row;
-        P[i] = pn;
+        Pnew[i] = pn;
         Qv[i] = qn;
         return (double)pn * (double)qn;
     }
 };
 
-// cg_b, recurrence form: x += alpha p, r -= alpha q; reduces r.z -> beta.
+// cg_b, recurrence form: r -= alpha q; reduces r.z -> beta.
 template <typename T>
 struct CgBQRows {
     static constexpr bool kDots = true;
-    struct Regs { T p, q, x, r; };
-    const T *P, *Qv;
-    T *X, *Rv;
+    struct Regs { T q, r; };
+    const T* Qv;
+    T* Rv;
     const double* alpha;
     T mrow;
     int64_t R;
     int row;
     __device__ __forceinline__ void load(int j, Regs& r) const {
         const int64_t i = (int64_t)j * R + row;
-        r.p = P[i];
         r.q = Qv[i];
-        r.x = X[i];
         r.r = Rv[i];
     }
     __device__ __forceinline__ double use(int j, const Regs& r) const {
         const T al = (T)alpha[j];
         const T res = r.r - al * r.q;
         const int64_t i = (int64_t)j * R + row;
-        X[i] = r.x + al * r.p;
         Rv[i] = res;
         return (double)res * (double)res * (double)mrow;
     }
@@ -348,6 +343,41 @@ struct CgBQRows {
 template <typename T>
 __device__ __forceinline__ T* vec(void* base) {
     return reinterpret_cast<T*>(base);
+}
+
+// search direction of CG iteration k: slice k of Ph, [NP][R] each
+template <typename T, int NP>
+__device__ __forceinline__ T* ph(const DevLayout& L, int k) {
+    return reinterpret_cast<T*>(L.Ph) + (int64_t)k * NP * L.R;
+}
+template <int NP>
+__device__ __forceinline__ const double* alpha_of(const DevLayout& L, int k, int inst) {
+    return L.alpha + ((int64_t)k * L.ninst + inst) * NP;
+}
+
+// x = x_0 + alpha_0 p_0 + alpha_1 p_1 + ...: the CG solution, formed once
+// from the stored directions in iteration order (the same sums, in the same
+// order, as updating x in every iteration).  A thread keeps its row's NP
+// values and loads one direction slice at a time, NP loads in flight.
+template <typename T, int NP>
+__global__ __launch_bounds__(TILE) void k_cg_x(DevLayout L, int tile_begin) {
+    FEL_ROW_LAYOUT();
+    const int inst = L.tile_inst[tile];
+    T* X = vec<T>(L.X);
+    T x[NP];
+#pragma unroll
+    for (int j = 0; j < NP; j++) x[j] = X[(int64_t)j * R + row];
+    for (int k = 0; k < L.K; k++) {
+        const T* p = ph<T, NP>(L, k);
+        const double* al = alpha_of<NP>(L, k, inst);
+        T v[NP];
+#pragma unroll
+        for (int j = 0; j < NP; j++) v[j] = p[(int64_t)j * R + row];
+#pragma unroll
+        for (int j = 0; j < NP; j++) x[j] = x[j] + (T)al[j] * v[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NP; j++) X[(int64_t)j * R + row] = x[j];
 }
 
 template <typename T, int W, int NP, int CH>
@@ -366,18 +396,18 @@ __global__ __launch_bounds__(TILE) void k_cg_init(DevLayout L, int tile_begin) {
 }
 
 template <typename T, int W, int NP, int CH>
-__global__ __launch_bounds__(TILE) void k_cg_a(DevLayout L, int tile_begin, int first, int flip) {
+__global__ __launch_bounds__(TILE) void k_cg_a(DevLayout L, int tile_begin, int first, int it) {
     FEL_ROW_LAYOUT();
     const int inst = L.tile_inst[tile];
     const T* Rv = vec<T>(L.Rv);
-    const T* Pold = vec<T>(flip ? L.Pa : L.Pb);
-    T* Pnew = vec<T>(flip ? L.Pb : L.Pa);
+    const T* Pold = ph<T, NP>(L, it > 0 ? it - 1 : 0);  // unread on the first iteration
+    T* Pnew = ph<T, NP>(L, it);
     const double* beta = L.beta + inst * NP;
     FEL_REDUCER(red, NP);
     if constexpr (q_recurrence<W>()) {
         auto go = [&](auto& b) {
             b.o.load(L, R, row);
-            b.Rv = Rv, b.P = vec<T>(L.Pa), b.Qv = vec<T>(L.Pb), b.beta = beta, b.R = R, b.row = row;
+            b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.Qv = vec<T>(L.Pa), b.beta = beta, b.R = R, b.row = row;
             run_rows<NP, CH>(b, &red);
         };
         if (first) {
@@ -402,17 +432,15 @@ __global__ __launch_bounds__(TILE) void k_cg_a(DevLayout L, int tile_begin, int 
 }
 
 template <typename T, int W, int NP, int CH>
-__global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int flip) {
+__global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int it) {
     FEL_ROW_LAYOUT();
     const int inst = L.tile_inst[tile];
     FEL_REDUCER(red, NP);
     if constexpr (q_recurrence<W>()) {
         CgBQRows<T> b;
-        b.P = vec<T>(L.Pa);
-        b.Qv = vec<T>(L.Pb);
-        b.X = vec<T>(L.X);
+        b.Qv = vec<T>(L.Pa);
         b.Rv = vec<T>(L.Rv);
-        b.alpha = L.alpha + inst * NP;
+        b.alpha = alpha_of<NP>(L, it, inst);
         b.mrow = ld<T>(L.minv, row);
         b.R = R;
         b.row = row;
@@ -420,10 +448,9 @@ __global__ __launch_bounds__(TILE) void k_cg_b(DevLayout L, int tile_begin, int 
     } else {
         CgBRows<T, W> b;
         b.o.load(L, R, row);
-        b.Pn = vec<T>(flip ? L.Pb : L.Pa);
-        b.X = vec<T>(L.X);
+        b.Pn = ph<T, NP>(L, it);
         b.Rv = vec<T>(L.Rv);
-        b.alpha = L.alpha + inst * NP;
+        b.alpha = alpha_of<NP>(L, it, inst);
         b.R = R;
         b.row = row;
         run_rows<NP, CH>(b, &red);
@@ -635,8 +662,8 @@ __global__ __launch_bounds__(FB_THREADS) void k_cg_a_fused(DevLayout L, int it) 
     };
     FEL_REDUCER_N(red, NP, FB_WAVES);
     const T* Rv = vec<T>(L.Rv);
-    const T* Pold = vec<T>(cur ? L.Pa : L.Pb);
-    T* Pnew = vec<T>(cur ? L.Pb : L.Pa);
+    const T* Pold = ph<T, NP>(L, it > 0 ? it - 1 : 0);  // unread on the first iteration
+    T* Pnew = ph<T, NP>(L, it);
     if (it == 0) {
         CgARows<T, W, true> b;
         b.o.load(L, R, row);
@@ -663,14 +690,15 @@ __global__ __launch_bounds__(FB_THREADS) void k_cg_b_fused(DevLayout L, int it) 
             const int j = threadIdx.x;
             const double rz = L.srz[((int64_t)(it & 1) * L.ninst + inst) * NP + j];
             alp[j] = (tot[j] != 0.0) ? rz / tot[j] : 0.0;
+            // the instance's first block keeps alpha for forming x (k_cg_x)
+            if (fb.w == 0) L.alpha[((int64_t)it * L.ninst + inst) * NP + j] = alp[j];
         }
         __syncthreads();
     };
     FEL_REDUCER_N(red, NP, FB_WAVES);
     CgBRows<T, W> b;
     b.o.load(L, R, row);
-    b.Pn = vec<T>((it & 1) ? L.Pb : L.Pa);
-    b.X = vec<T>(L.X);
+    b.Pn = ph<T, NP>(L, it);
     b.Rv = vec<T>(L.Rv);
     b.alpha = alp;
     b.R = R;
@@ -858,8 +886,8 @@ struct CgAQStaged {
     struct Own { T p, q; };
     LocalCols<W> l;
     T mv[W];
-    const T *Rv, *minv;
-    T *P, *Qv;
+    const T *Rv, *minv, *Pold;
+    T *Pnew, *Qv;
     const double* beta;
     int64_t R;
     int row;
@@ -868,7 +896,7 @@ struct CgAQStaged {
     __device__ __forceinline__ void keep(int j, Own& o) const {
         if constexpr (!FIRST) {
             const int64_t i = (int64_t)j * R + row;
-            o.p = P[i];
+            o.p = Pold[i];
             o.q = Qv[i];
         }
     }
@@ -880,7 +908,7 @@ struct CgAQStaged {
             qn += bet * o.q;
         }
         const int64_t i = (int64_t)j * R + row;
-        P[i] = pn;
+        Pnew[i] = pn;
         Qv[i] = qn;
         return (double)pn * (double)qn;
     }
@@ -890,27 +918,22 @@ struct CgAQStaged {
 template <typename T, int W>
 struct CgBStaged {
     static constexpr bool kDots = true;
-    struct Own { T x, r; };
+    struct Own { T r; };
     LocalCols<W> l;
     T mv[W], mrow;
     const T* Pn;
-    T *X, *Rv;
+    T* Rv;
     const double* alpha;
     int64_t R;
     int row;
     __device__ __forceinline__ T pre(int) const { return T(0); }
     __device__ __forceinline__ T stage(int j, int g, T) const { return Pn[(int64_t)j * R + g]; }
-    __device__ __forceinline__ void keep(int j, Own& o) const {
-        const int64_t i = (int64_t)j * R + row;
-        o.x = X[i];
-        o.r = Rv[i];
-    }
+    __device__ __forceinline__ void keep(int j, Own& o) const { o.r = Rv[(int64_t)j * R + row]; }
     __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
         const T qq = lds_row_product<T, W>(mv, l, st);
         const T al = (T)alpha[j];
         const int64_t i = (int64_t)j * R + row;
         const T res = o.r - al * qq;
-        X[i] = o.x + al * st[threadIdx.x];
         Rv[i] = res;
         return (double)res * (double)res * (double)mrow;
     }
@@ -994,7 +1017,7 @@ __global__ __launch_bounds__(TILE) void k_cg_init_lds(DevLayout L, int tile_begi
 }
 
 template <typename T, int W, int NP, int CH>
-__global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, int first, int flip) {
+__global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, int first, int it) {
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
     const int inst = L.tile_inst[tile];
@@ -1004,17 +1027,13 @@ __global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, 
         staged_row_setup<T, W>(b, L, R, row);
         b.minv = reinterpret_cast<const T*>(L.minv);
         b.Rv = vec<T>(L.Rv);
-        b.Pold = vec<T>(flip ? L.Pa : L.Pb);
-        b.Pnew = vec<T>(flip ? L.Pb : L.Pa);
+        b.Pold = ph<T, NP>(L, it > 0 ? it - 1 : 0);  // unread on the first iteration
+        b.Pnew = ph<T, NP>(L, it);
         b.beta = L.beta + inst * NP;
     };
     auto setup_q = [&](auto& b) {
-        staged_row_setup<T, W>(b, L, R, row);
-        b.minv = reinterpret_cast<const T*>(L.minv);
-        b.Rv = vec<T>(L.Rv);
-        b.P = vec<T>(L.Pa);
-        b.Qv = vec<T>(L.Pb);
-        b.beta = L.beta + inst * NP;
+        setup(b);
+        b.Qv = vec<T>(L.Pa);
     };
     if constexpr (q_recurrence<W>()) {
         if (first) {
@@ -1039,7 +1058,7 @@ __global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, 
 }
 
 template <typename T, int W, int NP, int CH>
-__global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, int flip) {
+__global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, int it) {
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
     const int inst = L.tile_inst[tile];
@@ -1048,11 +1067,9 @@ __global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, 
         // nothing to stage in the recurrence form (the host never selects
         // this kernel there); the direct rows keep it well defined
         CgBQRows<T> b;
-        b.P = vec<T>(L.Pa);
-        b.Qv = vec<T>(L.Pb);
-        b.X = vec<T>(L.X);
+        b.Qv = vec<T>(L.Pa);
         b.Rv = vec<T>(L.Rv);
-        b.alpha = L.alpha + inst * NP;
+        b.alpha = alpha_of<NP>(L, it, inst);
         b.mrow = ld<T>(L.minv, row);
         b.R = R;
         b.row = row;
@@ -1061,10 +1078,9 @@ __global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, 
         CgBStaged<T, W> b;
         staged_row_setup<T, W>(b, L, R, row);
         b.mrow = ld<T>(L.minv, row);
-        b.Pn = vec<T>(flip ? L.Pb : L.Pa);
-        b.X = vec<T>(L.X);
+        b.Pn = ph<T, NP>(L, it);
         b.Rv = vec<T>(L.Rv);
-        b.alpha = L.alpha + inst * NP;
+        b.alpha = alpha_of<NP>(L, it, inst);
         run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
     }
     red.finish(L, tile);
@@ -1154,18 +1170,16 @@ template <int Q, int W> struct CgInitBody {
     }
 };
 template <int Q, int W> struct CgABody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, bool first, bool flip, int ch,
-                          bool st, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, bool first, int it, int ch, bool st, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
-        FEL_SOLVER_LAUNCH(k_cg_a, ch, st, s, nt, L, tb, (int)first, (int)flip);
+        FEL_SOLVER_LAUNCH(k_cg_a, ch, st, s, nt, L, tb, (int)first, it);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct CgBBody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, bool flip, int ch, bool st,
-                          hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int it, int ch, bool st, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
-        FEL_SOLVER_LAUNCH(k_cg_b, ch, st, s, nt, L, tb, (int)flip);
+        FEL_SOLVER_LAUNCH(k_cg_b, ch, st, s, nt, L, tb, it);
         FEL_CHECK_LAUNCH();
     }
 };
@@ -1200,13 +1214,28 @@ hipError_t launch_cg_init(const DevLayout& L, int tb, int nt, int batch, bool st
                           hipStream_t s) {
     return dispatch_qw<CgInitBody>(L, tb, nt, batch, staged, s);
 }
-hipError_t launch_cg_a(const DevLayout& L, int tb, int nt, bool first, bool flip, int batch,
-                       bool staged, hipStream_t s) {
-    return dispatch_qw<CgABody>(L, tb, nt, first, flip, batch, staged, s);
-}
-hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, bool flip, int batch, bool staged,
+hipError_t launch_cg_a(const DevLayout& L, int tb, int nt, bool first, int it, int batch, bool staged,
                        hipStream_t s) {
-    return dispatch_qw<CgBBody>(L, tb, nt, flip, batch, staged, s);
+    if (it < 0 || it >= L.K || (!first && it == 0)) return hipErrorInvalidValue;
+    return dispatch_qw<CgABody>(L, tb, nt, first, it, batch, staged, s);
+}
+hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, int it, int batch, bool staged, hipStream_t s) {
+    if (it < 0 || it >= L.K) return hipErrorInvalidValue;
+    return dispatch_qw<CgBBody>(L, tb, nt, it, batch, staged, s);
+}
+hipError_t launch_cg_x(const DevLayout& L, int tb, int nt, hipStream_t s) {
+    (void)hipGetLastError();
+    const bool f64 = L.precision == 0;
+    if (L.Q == 9) {
+        if (f64) FEL_LAUNCH((k_cg_x<double, 16>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        else FEL_LAUNCH((k_cg_x<float, 16>), dim3(nt), dim3(TILE), 0, s, L, tb);
+    } else if (L.Q == 19) {
+        if (f64) FEL_LAUNCH((k_cg_x<double, 36>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        else FEL_LAUNCH((k_cg_x<float, 36>), dim3(nt), dim3(TILE), 0, s, L, tb);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 hipError_t launch_cheb_first(const DevLayout& L, int tb, int nt, int out0, double gamma, int batch,
                              bool staged, hipStream_t s) {
@@ -1250,11 +1279,13 @@ hipError_t launch_cg_init_fused(const DevLayout& L, int batch, hipStream_t s) {
 }
 hipError_t launch_cg_a_fused(const DevLayout& L, int it, int batch, hipStream_t s) {
     (void)hipGetLastError();
+    if (it < 0 || it >= L.K) return hipErrorInvalidValue;
     FEL_FUSED_LAUNCH(k_cg_a_fused, batch, s, L, it);
     return hipGetLastError();
 }
 hipError_t launch_cg_b_fused(const DevLayout& L, int it, int batch, hipStream_t s) {
     (void)hipGetLastError();
+    if (it < 0 || it >= L.K) return hipErrorInvalidValue;
     FEL_FUSED_LAUNCH(k_cg_b_fused, batch, s, L, it);
     return hipGetLastError();
 }
@@ -1265,15 +1296,17 @@ hipError_t launch_fused_check(const DevLayout& L, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int nvals, hipStream_t s) {
+hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int nvals, hipStream_t s,
+                           int it) {
     (void)hipGetLastError();
+    if (op == FIN_CG_A && (it < 0 || it >= L.K)) return hipErrorInvalidValue;
     const dim3 grid(ninst, nvals), block(FIN_THREADS);
     if (nvals == 16)
-        FEL_LAUNCH((k_finalize<16>), grid, block, 0, s, L, inst_begin, op);
+        FEL_LAUNCH((k_finalize<16>), grid, block, 0, s, L, inst_begin, op, it);
     else if (nvals == 36)
-        FEL_LAUNCH((k_finalize<36>), grid, block, 0, s, L, inst_begin, op);
+        FEL_LAUNCH((k_finalize<36>), grid, block, 0, s, L, inst_begin, op, it);
     else if (nvals == 8)
-        FEL_LAUNCH((k_finalize<8>), grid, block, 0, s, L, inst_begin, op);
+        FEL_LAUNCH((k_finalize<8>), grid, block, 0, s, L, inst_begin, op, it);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

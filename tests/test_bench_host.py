@@ -32,7 +32,7 @@ D3 = dict(Q=19, D=3, W=15, NB=9, s=4, sp=4, dev=True)
 
 @pytest.mark.parametrize("cls,per_row", [
     # 16 moving populations of 4 bytes; pattern 6 off-diagonal x 4 B; mass values 7 x 4 B; 1/m 4 B
-    ("cg_b", 5 * 64 + 24 + 28 + 4),          # read p x r, write x r
+    ("cg_b", 3 * 64 + 24 + 28 + 4),          # read p r, write r (x formed by cg_x)
     ("cg_a", 3 * 64 + 24 + 28 + 4),          # read r p_old, write p_new
     ("cg_init", 3 * 64 + 24 + 28 + 4),       # read rhs, write x r
     ("cheb", 4 * 64 + 24 + 28 + 4),          # read x_k rhs x_{k-1}, write x_{k+1}
@@ -48,13 +48,15 @@ def test_bytes_per_launch_match_the_reported_figures():
     """The per-launch figures quoted with the profiles: fused cg_b on the
     262,144-row channel, and the 3-D cg_a averaged over 17 iterations (the
     first one reads no previous direction)."""
-    assert bench.kernel_bytes("cg_b", **CH) * 262144 == 98566144
+    assert bench.kernel_bytes("cg_b", **CH) * 262144 == 65011712
+    # x = x_0 + sum of the 15 stored directions: read x and 15 directions, write x
+    assert bench.kernel_bytes("cg_x", K=15, **CH) == 17 * 64
     # 3-D (recurrence form): cg_a reads r p q and writes p q, the first of
-    # 17 iterations reads r only; cg_b streams p q x r, writes x r
+    # 17 iterations reads r only; cg_b streams q r, writes r
     first = 1.0 / 17
     per_launch = bench.kernel_bytes("cg_a", first_frac=first, **D3) * 2097152
     assert abs(per_launch - ((5 - 2 / 17) * 144 + 56 + 60 + 4) * 2097152) < 1.0
-    assert bench.kernel_bytes("cg_b", **D3) == 6 * 144 + 4
+    assert bench.kernel_bytes("cg_b", **D3) == 3 * 144 + 4
     # first iteration of cg_a in 2-D: two population passes instead of three
     assert bench.kernel_bytes("cg_a", first_frac=1.0, **CH) == 2 * 64 + 56
 
@@ -62,7 +64,7 @@ def test_bytes_per_launch_match_the_reported_figures():
 def test_fp64_plain_bytes():
     """FP64 plain: 8-byte values and populations, no references."""
     f64 = dict(Q=9, D=2, W=7, NB=5, s=8, sp=8, dev=False)
-    assert bench.kernel_bytes("cg_b", **f64) == 5 * 128 + 24 + 56 + 8
+    assert bench.kernel_bytes("cg_b", **f64) == 3 * 128 + 24 + 56 + 8
     # plain populations: the diagonal coefficients are read
     assert bench.kernel_bytes("stream", **f64) == 128 + 24 + 5 * 7 * 8 + 128
 
