@@ -88,7 +88,9 @@ typedef struct {
     int precision;        /* FEL_PREC_* */
     int mass_mode;        /* FEL_MASS_* */
     int cg_iters;         /* CG (or Chebyshev) iterations per solve; 0 = default (2-D: 30 FP64 / 15 FP32;
-                             3-D: 34 / 17) */
+                             3-D: 34 / 17).  The CG keeps every iteration's search direction (x is
+                             formed once after the last), so its workspace holds cg_iters vectors of
+                             2(Q-1) values per node row */
     double cg_tol;        /* after the last iteration, sqrt(r.z / r0.z0) above this flags FEL_ENOTCONV;
                              0 = default (1e-11 FP64, 1e-5 FP32) */
     int laplacian_mode;   /* FEL_LAP_* */
