@@ -3,6 +3,8 @@
 //
 //   k_cg_init / k_cg_a / k_cg_b   batched conjugate gradients, lumped
 //                                 preconditioner z = r / m, x0 = rhs / m
+//   k_cg_x                        x = x0 + sum_k alpha_k p_k from the stored
+//                                 directions, once after the last iteration
 //   k_finalize                    per-instance totals of the tile partials
 //                                 -> CG scalars (fixed summation order)
 //   k_cg_*_fused, k_fused_check   the same CG with the scalars formed by
