@@ -53,8 +53,8 @@ def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, 
     ref = 8 if dev else 0
     if cls == "stream":
         return NP * sp + ref + pat + NB * (W - 1 if dev else W) * s + NP * s
-    if cls == "cg_init":
-        return 3 * NP * s + pat + W * s + s
+    if cls == "cg_init":  # read rhs, write r (x_0 = rhs / m is formed again by cg_x)
+        return 2 * NP * s + pat + W * s + s
     qrec = W >= 15  # the CG carries q = M p by its own recurrence on the 3-D widths
     if cls == "cg_a":
         if qrec:  # read r, p, q; write p, q (the first iteration reads r only)
@@ -67,8 +67,8 @@ def kernel_bytes(cls: str, *, Q: int, D: int, W: int, NB: int, s: int, sp: int, 
         # read p, r; write r (M p formed again from neighbour values of p)
         return 3 * NP * s + pat + W * s + s
     if cls == "cg_x":
-        # x = x_0 + sum_k alpha_k p_k: read x and the K directions, write x
-        return (2 + K) * NP * s
+        # x = rhs / m + sum_k alpha_k p_k: read rhs, 1/m and the K directions, write x
+        return (2 + K) * NP * s + s
     if cls == "cheb_first":
         return 3 * NP * s + pat + W * s + s
     if cls == "cheb":

@@ -3,8 +3,9 @@
 //
 //   k_cg_init / k_cg_a / k_cg_b   batched conjugate gradients, lumped
 //                                 preconditioner z = r / m, x0 = rhs / m
-//   k_cg_x                        x = x0 + sum_k alpha_k p_k from the stored
-//                                 directions, once after the last iteration
+//   k_cg_x                        x = x0 + sum_k alpha_k p_k from the rhs and
+//                                 the stored directions, once after the last
+//                                 iteration (x0 itself is never stored)
 //   k_finalize                    per-instance totals of the tile partials
 //                                 -> CG scalars (fixed summation order)
 //   k_cg_*_fused, k_fused_check   the same CG with the scalars formed by
@@ -155,14 +156,15 @@ struct RowOps {
     }
 };
 
-// cg_init: X = rhs / m, r = rhs - M X, reduces r.z
+// cg_init: r = rhs - M x0 with x0 = rhs / m, reduces r.z (x0 is formed
+// again by cg_x, from the same operands, so it is not stored here)
 template <typename T, int W>
 struct CgInitRows {
     static constexpr bool kDots = true;
     struct Regs { T g[W]; T own; };
     RowOps<T, W, true> o;
     const T* rhs;
-    T *X, *Rv;
+    T* Rv;
     int64_t R;
     int row;
     bool live = true;  // false: a fused block's spare wave (loads only, no stores, zero terms)
@@ -180,7 +182,6 @@ struct CgInitRows {
         const T res = r.own - acc;
         const int64_t i = (int64_t)j * R + row;
         if (!live) return 0.0;
-        X[i] = r.own * o.mrow;
         Rv[i] = res;
         return (double)res * (double)res * (double)o.mrow;
     }
@@ -359,16 +360,23 @@ __device__ __forceinline__ const double* alpha_of(const DevLayout& L, int k, int
 
 // x = x_0 + alpha_0 p_0 + alpha_1 p_1 + ...: the CG solution, formed once
 // from the stored directions in iteration order (the same sums, in the same
-// order, as updating x in every iteration).  A thread keeps its row's NP
-// values and loads one direction slice at a time, NP loads in flight.
+// order, as updating x in every iteration).  x_0 = rhs / m is the product
+// cg_init takes, rounded on its own (not contracted into the first update).
+// A thread keeps its row's NP values and loads one direction slice at a
+// time, NP loads in flight.
 template <typename T, int NP>
 __global__ __launch_bounds__(TILE) void k_cg_x(DevLayout L, int tile_begin) {
     FEL_ROW_LAYOUT();
     const int inst = L.tile_inst[tile];
+    const T* rhs = vec<T>(L.Pb);
+    const T mrow = reinterpret_cast<const T*>(L.minv)[row];
     T* X = vec<T>(L.X);
     T x[NP];
+    {
+#pragma clang fp contract(off)
 #pragma unroll
-    for (int j = 0; j < NP; j++) x[j] = X[(int64_t)j * R + row];
+        for (int j = 0; j < NP; j++) x[j] = rhs[(int64_t)j * R + row] * mrow;
+    }
     for (int k = 0; k < L.K; k++) {
         const T* p = ph<T, NP>(L, k);
         const double* al = alpha_of<NP>(L, k, inst);
@@ -388,7 +396,6 @@ __global__ __launch_bounds__(TILE) void k_cg_init(DevLayout L, int tile_begin) {
     CgInitRows<T, W> b;
     b.o.load(L, R, row);
     b.rhs = vec<T>(L.Pb);
-    b.X = vec<T>(L.X);
     b.Rv = vec<T>(L.Rv);
     b.R = R;
     b.row = row;
@@ -633,7 +640,6 @@ __global__ __launch_bounds__(FB_THREADS) void k_cg_init_fused(DevLayout L) {
     CgInitRows<T, W> b;
     b.o.load(L, R, row);
     b.rhs = vec<T>(L.Pb);
-    b.X = vec<T>(L.X);
     b.Rv = vec<T>(L.Rv);
     b.R = R;
     b.row = row;
@@ -834,7 +840,7 @@ struct CgInitStaged {
     LocalCols<W> l;
     T mv[W], mrow;
     const T *rhs, *minv;
-    T *X, *Rv;
+    T* Rv;
     int64_t R;
     int row;
     __device__ __forceinline__ T pre(int g) const { return minv[g]; }
@@ -844,7 +850,6 @@ struct CgInitStaged {
         const T acc = lds_row_product<T, W>(mv, l, st);
         const T res = o.rhs - acc;
         const int64_t i = (int64_t)j * R + row;
-        X[i] = o.rhs * mrow;
         Rv[i] = res;
         return (double)res * (double)res * (double)mrow;
     }
@@ -1011,7 +1016,6 @@ __global__ __launch_bounds__(TILE) void k_cg_init_lds(DevLayout L, int tile_begi
     b.minv = reinterpret_cast<const T*>(L.minv);
     b.mrow = b.minv[row];
     b.rhs = vec<T>(L.Pb);
-    b.X = vec<T>(L.X);
     b.Rv = vec<T>(L.Rv);
     FEL_REDUCER(red, NP);
     run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);

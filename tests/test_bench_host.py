@@ -34,7 +34,7 @@ D3 = dict(Q=19, D=3, W=15, NB=9, s=4, sp=4, dev=True)
     # 16 moving populations of 4 bytes; pattern 6 off-diagonal x 4 B; mass values 7 x 4 B; 1/m 4 B
     ("cg_b", 3 * 64 + 24 + 28 + 4),          # read p r, write r (x formed by cg_x)
     ("cg_a", 3 * 64 + 24 + 28 + 4),          # read r p_old, write p_new
-    ("cg_init", 3 * 64 + 24 + 28 + 4),       # read rhs, write x r
+    ("cg_init", 2 * 64 + 24 + 28 + 4),       # read rhs, write r
     ("cheb", 4 * 64 + 24 + 28 + 4),          # read x_k rhs x_{k-1}, write x_{k+1}
     ("lumped", 2 * 64 + 4),
     # 16 stored deviations + 2 references, pattern, 5 x 6 off-diagonal basis values, 16 rhs values
@@ -49,8 +49,8 @@ def test_bytes_per_launch_match_the_reported_figures():
     262,144-row channel, and the 3-D cg_a averaged over 17 iterations (the
     first one reads no previous direction)."""
     assert bench.kernel_bytes("cg_b", **CH) * 262144 == 65011712
-    # x = x_0 + sum of the 15 stored directions: read x and 15 directions, write x
-    assert bench.kernel_bytes("cg_x", K=15, **CH) == 17 * 64
+    # x = rhs / m + sum of the 15 stored directions: read rhs, 1/m and 15 directions, write x
+    assert bench.kernel_bytes("cg_x", K=15, **CH) == 17 * 64 + 4
     # 3-D (recurrence form): cg_a reads r p q and writes p q, the first of
     # 17 iterations reads r only; cg_b streams q r, writes r
     first = 1.0 / 17
