@@ -886,8 +886,8 @@ hipError_t enqueue_solve(fel_ctx* c) {
                 hipSuccess)
                 return e;
         }
-        if ((e = timed(c, KC_FINALIZE, [&] { return launch_fused_check(L, s); })) != hipSuccess) return e;
-        return timed(c, KC_CG_X, [&] { return launch_cg_x(L, tb, nt, s); });
+        // cg_x also runs the final residual check on the last cg_b's partials
+        return timed(c, KC_CG_X, [&] { return launch_cg_x(L, tb, nt, true, s); });
     }
     const int ni = c->ninst, np = c->NP;
     auto fin = [&](int op, int it = 0) {
@@ -910,7 +910,7 @@ hipError_t enqueue_solve(fel_ctx* c) {
             return e;
         if ((e = fin(it == c->cg_iters - 1 ? 3 : 2)) != hipSuccess) return e;
     }
-    return timed(c, KC_CG_X, [&] { return launch_cg_x(L, tb, nt, s); });
+    return timed(c, KC_CG_X, [&] { return launch_cg_x(L, tb, nt, false, s); });
 }
 
 // Chooses the schedule of each solver kernel left to the tuner: the

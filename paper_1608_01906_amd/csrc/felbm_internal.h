@@ -127,7 +127,7 @@ hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool firs
 hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, int it, int batch, bool staged,
                        hipStream_t s);
 // x += sum over the K iterations of alpha_k p_k, in iteration order
-hipError_t launch_cg_x(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+hipError_t launch_cg_x(const DevLayout& L, int tile_begin, int ntiles, bool check, hipStream_t s);
 // op: 0 CG init, 1 alpha, 2 beta, 3 final residual check, 4 conserved sums;
 // nvals values per tile (partials stored population-major)
 hipError_t launch_finalize(const DevLayout& L, int inst_begin, int ninst, int op, int nvals, hipStream_t s,
@@ -138,7 +138,6 @@ hipError_t launch_lumped(const DevLayout& L, int tile_begin, int ntiles, hipStre
 hipError_t launch_cg_init_fused(const DevLayout& L, int batch, hipStream_t s);
 hipError_t launch_cg_a_fused(const DevLayout& L, int it, int batch, hipStream_t s);
 hipError_t launch_cg_b_fused(const DevLayout& L, int it, int batch, hipStream_t s);
-hipError_t launch_fused_check(const DevLayout& L, hipStream_t s);
 // ELL widths from which the CG carries q = M p by its own recurrence (the
 // 3-D layouts, where neighbour gathers dominate): the second CG kernel then
 // reads own rows only and has no staged form.

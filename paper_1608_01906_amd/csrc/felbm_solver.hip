@@ -8,8 +8,9 @@
 //                                 iteration (x0 itself is never stored)
 //   k_finalize                    per-instance totals of the tile partials
 //                                 -> CG scalars (fixed summation order)
-//   k_cg_*_fused, k_fused_check   the same CG with the scalars formed by
-//                                 every block of the next launch (2-D)
+//   k_cg_*_fused                  the same CG with the scalars formed by
+//                                 every block of the next launch (2-D; the
+//                                 final residual check then runs in k_cg_x)
 //   k_cheb_first / k_cheb         Chebyshev semi-iteration, no reductions
 //   *_lds                         LDS-staged forms of the above (neighbour
 //                                 values read from a per-tile stage)
@@ -363,9 +364,14 @@ __device__ __forceinline__ const double* alpha_of(const DevLayout& L, int k, int
 // order, as updating x in every iteration).  x_0 = rhs / m is the product
 // cg_init takes, rounded on its own (not contracted into the first update).
 // A thread keeps its row's NP values and loads one direction slice at a
-// time, NP loads in flight.
+// time, NP loads in flight.  With check set (after the fused CG), the first
+// wave of each block also takes the residual checks c = blockIdx.x,
+// blockIdx.x + gridDim.x, ... of the ninst * NP (instance, value) pairs,
+// which saves the fused path a launch of its own for them.
+template <int NP>
+__device__ __forceinline__ void fused_residual_check(const DevLayout& L, int inst, int j);
 template <typename T, int NP>
-__global__ __launch_bounds__(TILE) void k_cg_x(DevLayout L, int tile_begin) {
+__global__ __launch_bounds__(TILE) void k_cg_x(DevLayout L, int tile_begin, int check) {
     FEL_ROW_LAYOUT();
     const int inst = L.tile_inst[tile];
     const T* rhs = vec<T>(L.Pb);
@@ -388,6 +394,8 @@ __global__ __launch_bounds__(TILE) void k_cg_x(DevLayout L, int tile_begin) {
     }
 #pragma unroll
     for (int j = 0; j < NP; j++) X[(int64_t)j * R + row] = x[j];
+    if (check && threadIdx.x < 64)
+        for (int c = blockIdx.x; c < L.ninst * NP; c += gridDim.x) fused_residual_check<NP>(L, c / NP, c % NP);
 }
 
 template <typename T, int W, int NP, int CH>
@@ -716,16 +724,18 @@ __global__ __launch_bounds__(FB_THREADS) void k_cg_b_fused(DevLayout L, int it) 
     red.finish_to(L.fpart0, L.nfb, pidx, FB_WAVES);
 }
 
-// final residual check: r.z after the last iteration against r0.z0
+// Final residual check of the fused CG, run by one whole wavefront: r.z
+// after the last iteration (the fused blocks' partials, summed in a fixed
+// order) against r0.z0 for value j of an instance.
 template <int NP>
-__global__ __launch_bounds__(64) void k_fused_check(DevLayout L) {
-    const int inst = blockIdx.x, j = blockIdx.y;
+__device__ __forceinline__ void fused_residual_check(const DevLayout& L, int inst, int j) {
     const InstParams& P = L.params[inst];
     const double* p = L.fpart0 + (int64_t)j * L.nfb + P.fb_begin;
+    const int lane = threadIdx.x & 63;
     double s = 0.0;
-    for (int b = threadIdx.x; b < P.fb_count; b += 64) s += p[b];
+    for (int b = lane; b < P.fb_count; b += 64) s += p[b];
     s = wave_sum(s);
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         const double r0 = L.rz0[inst * NP + j];
         if (r0 > 0.0 && !(s <= L.cg_tol2 * r0)) atomicOr(L.status, 2u);
     }
@@ -1229,15 +1239,18 @@ hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, int it, int batch, bo
     if (it < 0 || it >= L.K) return hipErrorInvalidValue;
     return dispatch_qw<CgBBody>(L, tb, nt, it, batch, staged, s);
 }
-hipError_t launch_cg_x(const DevLayout& L, int tb, int nt, hipStream_t s) {
+hipError_t launch_cg_x(const DevLayout& L, int tb, int nt, bool check, hipStream_t s) {
     (void)hipGetLastError();
+    // the residual check reads the fused CG's partials, which exist for the 2-D lattice only
+    if (nt <= 0 || (check && (L.Q != 9 || L.nfb <= 0))) return hipErrorInvalidValue;
     const bool f64 = L.precision == 0;
+    const int ck = check ? 1 : 0;
     if (L.Q == 9) {
-        if (f64) FEL_LAUNCH((k_cg_x<double, 16>), dim3(nt), dim3(TILE), 0, s, L, tb);
-        else FEL_LAUNCH((k_cg_x<float, 16>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        if (f64) FEL_LAUNCH((k_cg_x<double, 16>), dim3(nt), dim3(TILE), 0, s, L, tb, ck);
+        else FEL_LAUNCH((k_cg_x<float, 16>), dim3(nt), dim3(TILE), 0, s, L, tb, ck);
     } else if (L.Q == 19) {
-        if (f64) FEL_LAUNCH((k_cg_x<double, 36>), dim3(nt), dim3(TILE), 0, s, L, tb);
-        else FEL_LAUNCH((k_cg_x<float, 36>), dim3(nt), dim3(TILE), 0, s, L, tb);
+        if (f64) FEL_LAUNCH((k_cg_x<double, 36>), dim3(nt), dim3(TILE), 0, s, L, tb, ck);
+        else FEL_LAUNCH((k_cg_x<float, 36>), dim3(nt), dim3(TILE), 0, s, L, tb, ck);
     } else {
         return hipErrorInvalidValue;
     }
@@ -1293,12 +1306,6 @@ hipError_t launch_cg_b_fused(const DevLayout& L, int it, int batch, hipStream_t 
     (void)hipGetLastError();
     if (it < 0 || it >= L.K) return hipErrorInvalidValue;
     FEL_FUSED_LAUNCH(k_cg_b_fused, batch, s, L, it);
-    return hipGetLastError();
-}
-hipError_t launch_fused_check(const DevLayout& L, hipStream_t s) {
-    (void)hipGetLastError();
-    if (L.Q != 9 || L.nfb <= 0) return hipErrorInvalidValue;
-    FEL_LAUNCH((k_fused_check<16>), dim3(L.ninst, 16), dim3(64), 0, s, L);
     return hipGetLastError();
 }
 

@@ -41,16 +41,13 @@ def device_source_hash() -> str:
 
 def kernel_class(name: str) -> str | None:
     """Kernel class (as in fel_profile_read) of a demangled kernel name:
-    LDS-staged and fused forms count as their kernel, the fused residual
-    check as a finalize."""
+    LDS-staged and fused forms count as their kernel."""
     m = re.search(r"fel::(k_[a-z_0-9]+?)(?:_lds|_fused)?(?:<|\()", name)
     if not m:
         return None
     k = m.group(1)[2:]
     if k.startswith("cheb"):
         return "cheb"
-    if k == "fused_check":
-        return "finalize"
     for suffix in ("_plain", "_dev"):
         if k.endswith(suffix):
             k = k[: -len(suffix)]

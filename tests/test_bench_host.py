@@ -75,7 +75,7 @@ def test_fp64_plain_bytes():
     ("void fel::k_cg_init<float, 7, 16, 2>(fel::DevLayout, int)", "cg_init"),
     ("void fel::k_cheb_first_lds<float, 7, 16, 4>(fel::DevLayout, int, int, double)", "cheb"),
     ("void fel::k_cheb<float, 7, 16, 2>(fel::DevLayout, int, int, double, double)", "cheb"),
-    ("void fel::k_fused_check<16>(fel::DevLayout)", "finalize"),
+    ("void fel::k_cg_x<float, 16>(fel::DevLayout, int, int)", "cg_x"),
     ("void fel::k_finalize<36>(fel::DevLayout, int, int)", "finalize"),
     ("void fel::k_stream_dev<9, 7, float>(fel::DevLayout, int)", "stream"),
     ("void fel::k_collide_plain<19, 15>(fel::DevLayout, int)", "collide"),
