@@ -383,6 +383,10 @@ __global__ __launch_bounds__(TILE) void k_cg_x(DevLayout L, int tile_begin, int 
 #pragma unroll
         for (int j = 0; j < NP; j++) x[j] = rhs[(int64_t)j * R + row] * mrow;
     }
+    // two (D2Q9) or four (D3Q19) directions per trip: the next slices' loads
+    // are issued before the current ones are summed
+    constexpr int kDirUnroll = NP <= 16 ? 2 : 4;
+#pragma unroll kDirUnroll
     for (int k = 0; k < L.K; k++) {
         const T* p = ph<T, NP>(L, k);
         const double* al = alpha_of<NP>(L, k, inst);
