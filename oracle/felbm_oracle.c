@@ -8,7 +8,10 @@
  * It is written to be checked against the paper by eye: scalar loops over
  * elements and nodes, no blocking, no fusion, no assembled sparse matrix.
  * Every operator is applied element by element from the element volume and
- * the constant gradients of the linear shape functions.
+ * the constant gradients of the linear shape functions.  The only
+ * concurrency is across populations in the streaming stage (OpenMP, one
+ * population per thread at a time), which leaves every population's
+ * arithmetic and its order unchanged.
  *
  *  - Streaming (Section 2.2.1, Taylor expansion and Galerkin weak form):
  *      M (psi^{n+1} - psi^n) = -(dt C_a + dt^2 D_a) psi^n
@@ -48,6 +51,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL -1
@@ -132,6 +138,7 @@ typedef struct orc {
     double *delta;             /* [2Q][N] streaming increments of the last step */
     int last_cg_iters;
     double last_cg_relres;
+    int threads;               /* threads over populations (0 = the OpenMP default) */
 } orc;
 
 static void *xcalloc(size_t n, size_t s) { return calloc(n ? n : 1, s); }
@@ -611,39 +618,59 @@ int orc_init(orc *o, const double *rho, const double *u, const double *p) {
     return ORC_OK;
 }
 
+/* Streams one population: M Delta = -(dt C_a + dt^2 D_a) psibar,
+ * psibar_s = psibar + Delta.  Touches only that population's slices, so
+ * the populations of a step are independent of each other. */
+static int stream_population(orc *o, int pop, int *iters, double *relres) {
+    int64_t N = o->N;
+    int a = pop % o->L.Q;
+    double *x = &o->psibar[(int64_t)pop * N];
+    double *d = &o->delta[(int64_t)pop * N];
+    double *rhs = (double *)xcalloc((size_t)N, sizeof(double));
+    if (!rhs) return ORC_ENOMEM;
+    int rc = ORC_OK;
+    *iters = 0;
+    *relres = 0.0;
+    orc_apply_A(o, a, x, rhs);
+    for (int64_t k = 0; k < N; k++) rhs[k] = -rhs[k];
+    if (o->mass_mode == 1) {
+        for (int64_t k = 0; k < N; k++) d[k] = rhs[k] / o->mlump[k];
+    } else {
+        rc = orc_solve_M(o, rhs, d, iters, relres);
+    }
+    if (rc != ORC_ENOMEM)
+        for (int64_t k = 0; k < N; k++) x[k] += d[k];
+    free(rhs);
+    return rc;
+}
+
 static int one_step(orc *o) {
     int64_t N = o->N;
     int Q = o->L.Q, dim = o->dim;
     const lattice_t *L = &o->L;
-    double *rhs = (double *)xcalloc((size_t)N, sizeof(double));
-    if (!rhs) return ORC_ENOMEM;
     int rc = ORC_OK;
     int maxit = 0;
     double worst = 0.0;
 
-    /* Streaming: M Delta = -(dt C + dt^2 D) psibar, psibar_s = psibar + Delta */
+    /* Streaming of all 2Q populations.  Each population is streamed and
+     * solved on its own (the same operations in the same order whatever the
+     * thread count, so the result does not depend on it); with OpenMP the
+     * populations are spread over threads. */
+    int pop_rc[38], pop_it[38];
+    double pop_rel[38];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(o->threads > 0 ? o->threads : omp_get_max_threads())
+#endif
+    for (int pop = 0; pop < 2 * Q; pop++)
+        pop_rc[pop] = stream_population(o, pop, &pop_it[pop], &pop_rel[pop]);
     for (int pop = 0; pop < 2 * Q; pop++) {
-        int a = pop % Q;
-        double *x = &o->psibar[(int64_t)pop * N];
-        double *d = &o->delta[(int64_t)pop * N];
-        orc_apply_A(o, a, x, rhs);
-        for (int64_t k = 0; k < N; k++) rhs[k] = -rhs[k];
-        if (o->mass_mode == 1) {
-            for (int64_t k = 0; k < N; k++) d[k] = rhs[k] / o->mlump[k];
-        } else {
-            int it;
-            double rel;
-            int src = orc_solve_M(o, rhs, d, &it, &rel);
-            if (src == ORC_ENOMEM) { free(rhs); return src; }
-            if (src == ORC_ENOTCONV) rc = ORC_ENOTCONV;
-            if (it > maxit) maxit = it;
-            if (rel > worst) worst = rel;
-        }
-        for (int64_t k = 0; k < N; k++) x[k] += d[k];
+        if (pop_rc[pop] == ORC_ENOMEM) return ORC_ENOMEM;
+        if (pop_rc[pop] == ORC_ENOTCONV) rc = ORC_ENOTCONV;
+        if (pop_it[pop] > maxit) maxit = pop_it[pop];
+        if (pop_rel[pop] > worst) worst = pop_rel[pop];
     }
     o->last_cg_iters = maxit;
     o->last_cg_relres = worst;
-    free(rhs);
 
     /* Walls: populations entering the fluid take the value of their opposite */
     for (int64_t k = 0; k < N; k++) {
@@ -788,6 +815,23 @@ int orc_set_state(orc *o, const double *psibar) {
     memcpy(o->psibar, psibar, (size_t)2 * o->L.Q * o->N * sizeof(double));
     o->have_state = 1;
     return ORC_OK;
+}
+
+/* Threads the streaming of a step's populations may use (0 = the OpenMP
+ * default; 1 = serial).  Results do not depend on it. */
+int orc_set_threads(orc *o, int n) {
+    if (n < 0) return ORC_EINVAL;
+    o->threads = n;
+    return ORC_OK;
+}
+
+/* Threads the OpenMP runtime offers by default (1 without OpenMP). */
+int orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 int orc_beta_kappa(const orc *o, double *bk) {

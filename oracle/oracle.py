@@ -26,7 +26,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -47,7 +47,8 @@ def _load():
         for name in ["orc_set_phys", "orc_set_options", "orc_apply_M", "orc_apply_A",
                      "orc_recover_grad", "orc_lumped_mass", "orc_solve_M", "orc_node_terms",
                      "orc_init", "orc_step", "orc_fields", "orc_aux", "orc_last_cg",
-                     "orc_conserved", "orc_get_state", "orc_set_state", "orc_beta_kappa"]:
+                     "orc_conserved", "orc_get_state", "orc_set_state", "orc_beta_kappa",
+                     "orc_weak_laplacian", "orc_set_threads", "orc_max_threads"]:
             getattr(lib, name).restype = C.c_int
         lib.orc_set_phys.argtypes = [C.c_void_p, _dp]
         lib.orc_set_options.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int]
@@ -66,6 +67,9 @@ def _load():
         lib.orc_get_state.argtypes = [C.c_void_p, _dp]
         lib.orc_set_state.argtypes = [C.c_void_p, _dp]
         lib.orc_beta_kappa.argtypes = [C.c_void_p, _dp]
+        lib.orc_weak_laplacian.argtypes = [C.c_void_p, _dp, _dp]
+        lib.orc_set_threads.argtypes = [C.c_void_p, C.c_int]
+        lib.orc_max_threads.argtypes = []
         _lib = lib
     return _lib
 
@@ -179,7 +183,19 @@ class Oracle:
         a = np.ascontiguousarray(psibar, np.float64).reshape(2 * self.Q, self.N)
         _check(self.lib.orc_set_state(self.h, _d(a)), "set_state")
 
+    def set_threads(self, n: int):
+        """Threads over populations in the streaming stage (0 = OpenMP
+        default, 1 = serial); results do not depend on it."""
+        _check(self.lib.orc_set_threads(self.h, int(n)), "set_threads")
+
     # -- operators (for the pins) --------------------------------------------
+    def weak_laplacian(self, phi):
+        """-m^-1 K phi, K = int grad N . grad N^T (natural boundary)."""
+        phi = np.ascontiguousarray(phi, np.float64)
+        out = np.zeros(self.N)
+        _check(self.lib.orc_weak_laplacian(self.h, _d(phi), _d(out)), "weak_laplacian")
+        return out
+
     def apply_M(self, x):
         x = np.ascontiguousarray(x, np.float64)
         y = np.zeros(self.N)
@@ -224,6 +240,11 @@ class Oracle:
         outs = [np.zeros(self.Q) for _ in range(5)]
         _check(self.lib.orc_node_terms(self.h, _d(v), *[_d(o) for o in outs]), "node_terms")
         return dict(zip(["feq", "geq", "F", "G", "Gb"], outs))
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP runtime uses by default."""
+    return int(_load().orc_max_threads())
 
 
 def run(instance, lattice: int, steps: int, **kw):
