@@ -150,3 +150,17 @@ def test_measured_traffic_only_for_current_sources(tmp_path, monkeypatch):
     rec["kernel_source_sha256_16"] = "0" * 16
     path.write_text(json.dumps(rec))
     assert bench.measured_traffic("channel2d", "fp32", 0, "cg_b", "fel::k_cg_b<float, 7, 16, 2>") is None
+
+
+@pytest.mark.parametrize("D,precision,k,mass_mode,expect", [
+    (2, "fp64", 30, 0, 31020), (2, "fp32", 15, 0, 8688), (2, "fp32_fp16", 15, 0, 8562),
+    (3, "fp64", 34, 0, 74144), (3, "fp32", 17, 0, 20712),
+    (2, "fp32", 15, 1, 960), (3, "fp32", 17, 1, 2368)])
+def test_whole_step_byte_model(D, precision, k, mass_mode, expect):
+    """The whole-step bytes per node of the measurement's byte model, at the
+    figures it tabulates (FP64 plain, FP32, FP16 storage; lumped mass)."""
+    assert bench.survey_bytes_per_node(D, precision, k, mass_mode) == expect
+
+
+def test_whole_step_byte_model_has_no_chebyshev_figure():
+    assert bench.survey_bytes_per_node(2, "fp32", 15, 2) is None

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_1608_01906_amd.inputs import rt2d, droplet3d, ensemble2d, channel2d
-from tests._parity import compare_fields
+from tests._parity import compare_fields, fp16_storage_bound, max_deviation
 
 pytestmark = pytest.mark.gpu
 
@@ -29,19 +29,29 @@ def _oracle(oracle_mod, inst, lattice, steps):
     return o
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", TOL32), ("fp32_fp16", 2e-3)])
-def test_rayleigh_taylor_reduced(felbm, oracle_mod, precision, tol):
-    """Heavy over light between walls with gravity, 32 x 96 nodes."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_fp16"])
+def test_rayleigh_taylor_reduced(felbm, oracle_mod, precision):
+    """Heavy over light between walls with gravity, 32 x 96 nodes, 40 steps:
+    FP64 within 1e-11, FP32 within 2e-5 on rho, u and C; FP16 storage on rho
+    and C within its rounding bound over the oracle's largest deviation."""
     w = rt2d(nx=32, ny=96)
     inst = w.instances[0]
+    steps = 40
     ctx = felbm.from_workload(w, precision=precision)
-    ctx.step(40)
+    ctx.step(steps)
     ctx.sync()
-    o = _oracle(oracle_mod, inst, 9, 40)
+    o = _oracle(oracle_mod, inst, 9, 0)
+    md = max_deviation(o.get_state(), o.fields(), 9)
+    o.step(steps)
+    md = max(md, max_deviation(o.get_state(), o.fields(), 9))
     e = compare_fields(ctx.read_fields(0), o.fields(), inst)
     print("rt", precision, e, flush=True)
-    for k in ("rho", "u", "C"):
-        assert e[k] < tol, (k, e[k])
+    if precision == "fp32_fp16":
+        tol, keys = fp16_storage_bound(md, inst.phys.rho_l, inst.phys.rho_v, steps), ("rho", "C")
+    else:
+        tol, keys = {"fp64": 1e-11, "fp32": TOL32}[precision], ("rho", "u", "C")
+    for k in keys:
+        assert e[k] < tol, (k, e[k], tol)
 
 
 def test_droplet3d_full_size_laplace(felbm):
@@ -165,7 +175,13 @@ def test_channel_full_length_keeps_analytic_profile(felbm, precision):
 def test_rayleigh_taylor_full_size_fp16_vs_fp32(felbm):
     """1024 x 4096 Rayleigh-Taylor (4.2 M nodes) over its full 2000 steps with
     FP16 and FP32 deviation storage: both stay finite, keep the heavy-phase
-    volume, and the FP16 fields stay within 2e-3 of the FP32 ones."""
+    volume, and the FP16 fields stay within 2e-3 of the FP32 ones.  The
+    worst-case FP16 rounding bound grows linearly with the steps (0.04
+    here); roundings of independent sign add up as the square root of the
+    steps, sqrt(2000) 2^-11 max|delta| / (rho_l - rho_v) = 8.8e-4 at the
+    largest deviation 0.027 of this workload's oracle states (0.025 at t = 0,
+    0.027 after 40 steps on the 32 x 96 and 64 x 256 meshes), and the 2e-3
+    bound allows about twice that."""
     w = rt2d()
     inst = w.instances[0]
     out = {}

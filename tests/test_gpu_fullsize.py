@@ -1,0 +1,140 @@
+"""Full-size parity with the FP64 oracle for the large workloads, in the
+launch configuration the benchmark times (default options: schedules chosen
+by the tuner, graph-replayed steps):
+
+  rt2d        1024 x 4096 Rayleigh-Taylor, walls, 4.2 M nodes in one
+              instance (16,384 tiles: the finalize reductions run their
+              multi-round loop)
+  droplet3d   128^3 Kuhn-tet droplet, D3Q19, 2.1 M nodes
+  ensemble2d  all 64 drops of the batched ensemble, 6.58 M nodes, every
+              instance compared on its own
+
+Each runs a short prefix (the oracle streams its populations on all host
+threads; one step of the 3-D droplet is still about a minute of CPU time).
+Bounds (norms and derivations in tests/_parity.py): 1e-11 for the FP64
+path and 2e-5 for FP32 storage on rho, u and C with the error-norm floors;
+for FP16 storage on rho and C the bound of one FP16 rounding of every stored
+deviation per step, over the largest deviation of the oracle's states; the
+velocity error with no floor within the rounding bound of each precision.
+"""
+import gc
+
+import numpy as np
+import pytest
+
+from paper_1608_01906_amd.inputs import droplet3d, ensemble2d, rt2d
+from tests._parity import U16, U32, U64, compare_fields, fp16_storage_bound, max_deviation, velocity_bound
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-11, "fp32": 2e-5}
+
+
+@pytest.fixture(scope="module")
+def felbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_01906_amd import felbm as F
+    F.load_library()
+    return F
+
+
+def _oracle_fields(oracle_mod, w, steps):
+    """Fields of every instance after `steps` oracle steps, and per instance
+    the largest deviation |psi_a / w_a - ref| of its initial and final
+    states."""
+    out, devs = [], []
+    for inst in w.instances:
+        o = oracle_mod.Oracle(inst.mesh, w.lattice, inst.phys)
+        o.init(inst.rho0, inst.u0, inst.p0)
+        d0 = max_deviation(o.get_state(), o.fields(), w.lattice)
+        o.step(steps)
+        out.append(o.fields())
+        devs.append(max(d0, max_deviation(o.get_state(), out[-1], w.lattice)))
+        del o
+    gc.collect()
+    return out, devs
+
+
+def _device_fields(felbm, w, precision, steps):
+    import torch
+    ctx = felbm.from_workload(w, precision=precision)
+    ctx.step(steps)
+    ctx.sync()
+    f = [ctx.read_fields(i) for i in range(len(w.instances))]
+    sched = ctx.tuning()
+    ctx.close()
+    del ctx
+    gc.collect()
+    torch.cuda.empty_cache()
+    return f, sched
+
+
+EPS = {"fp64": U64, "fp32": U32, "fp32_fp16": U16}
+
+
+def _check(w, dev, case, precision, label, steps):
+    orc, devs = case
+    dim = 2 if w.lattice == 9 else 3
+    worst = {}
+    for i, (d, o, inst, md) in enumerate(zip(dev, orc, w.instances, devs)):
+        e = compare_fields(d, o, inst)
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+        if precision == "fp32_fp16":
+            tol = fp16_storage_bound(md, inst.phys.rho_l, inst.phys.rho_v, steps)
+            keys = ("rho", "C")
+        else:
+            tol, keys = TOL[precision], ("rho", "u", "C")
+        for k in keys:
+            assert e[k] < tol, (label, precision, i, k, e[k], tol)
+        ub = velocity_bound(md, inst.phys.rho_v, float(np.abs(o["u"]).max()), dim, steps, EPS[precision],
+                            arith=TOL.get(precision, 2e-5))
+        assert e["u_rel"] < ub, (label, precision, i, "u_rel", e["u_rel"], ub)
+    print(label, precision, {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+
+
+@pytest.fixture(scope="module")
+def rt_case(oracle_mod):
+    w = rt2d()
+    print("rt2d full size:", w.n_nodes, "nodes, oracle 1 step", flush=True)
+    return w, _oracle_fields(oracle_mod, w, 1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_fp16"])
+def test_rt2d_full_size_vs_oracle(felbm, rt_case, precision):
+    w, case = rt_case
+    dev, sched = _device_fields(felbm, w, precision, 1)
+    print("rt2d schedule", sched, flush=True)
+    _check(w, dev, case, precision, "rt2d 1024x4096, 1 step", 1)
+
+
+@pytest.fixture(scope="module")
+def droplet3d_case(oracle_mod):
+    w = droplet3d()
+    print("droplet3d full size:", w.n_nodes, "nodes, oracle 1 step", flush=True)
+    return w, _oracle_fields(oracle_mod, w, 1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_droplet3d_full_size_vs_oracle(felbm, droplet3d_case, precision):
+    w, case = droplet3d_case
+    dev, sched = _device_fields(felbm, w, precision, 1)
+    print("droplet3d schedule", sched, flush=True)
+    _check(w, dev, case, precision, "droplet3d 128^3, 1 step", 1)
+
+
+@pytest.fixture(scope="module")
+def ensemble_case(oracle_mod):
+    w = ensemble2d()
+    print("ensemble2d full size:", len(w.instances), "instances,", w.n_nodes, "nodes, oracle 2 steps", flush=True)
+    return w, _oracle_fields(oracle_mod, w, 2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ensemble_full_size_every_instance_vs_oracle(felbm, ensemble_case, precision):
+    w, case = ensemble_case
+    dev, sched = _device_fields(felbm, w, precision, 2)
+    print("ensemble schedule", sched, flush=True)
+    _check(w, dev, case, precision, "ensemble 64 drops, 2 steps", 2)
