@@ -44,15 +44,21 @@ def _oracle_fields(oracle_mod, w, steps):
     """Fields of every instance after `steps` oracle steps, and per instance
     the largest deviation |psi_a / w_a - ref| of its initial and final
     states."""
+    import time
     out, devs = [], []
-    for inst in w.instances:
+    t0 = time.perf_counter()
+    for i, inst in enumerate(w.instances):
         o = oracle_mod.Oracle(inst.mesh, w.lattice, inst.phys)
         o.init(inst.rho0, inst.u0, inst.p0)
         d0 = max_deviation(o.get_state(), o.fields(), w.lattice)
+        if len(w.instances) == 1:
+            print(f"  oracle set up ({time.perf_counter() - t0:.0f} s), stepping", flush=True)
         o.step(steps)
         out.append(o.fields())
         devs.append(max(d0, max_deviation(o.get_state(), out[-1], w.lattice)))
         del o
+        if len(w.instances) == 1 or i % 8 == 7:
+            print(f"  oracle instance {i} done ({time.perf_counter() - t0:.0f} s)", flush=True)
     gc.collect()
     return out, devs
 
