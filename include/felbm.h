@@ -165,6 +165,28 @@ FEL_API fel_status fel_workspace_size(fel_ctx* ctx, size_t* bytes);
  * stream) all work is ordered on; copies the operators to the device. */
 FEL_API fel_status fel_bind(fel_ctx* ctx, void* dev_ptr, size_t bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): fel_bind
+ * without a caller buffer.  The context is bound to the library's own
+ * static device array of FEL_STATIC_WORKSPACE_BYTES per GPU (the current
+ * device's; each GPU holds its copy until the process ends), found once per
+ * device by symbol lookup; the call allocates no device memory.
+ *  - The uploaded meshes must fit: fel_workspace_size <= FEL_STATIC_WORKSPACE_BYTES,
+ *    else FEL_ENOMEM and the context stays unbound.
+ *  - Schedules the options leave to timing take fixed defaults instead
+ *    (population batch 2, direct gathers, finalize-launch reductions), and
+ *    fel_step launches its kernels directly, with no graph of the library's
+ *    own (so the caller may capture fel_step after its first call).
+ *  - One array per GPU serves every context bound this way on that GPU: it
+ *    keeps the last user's contents (the bind clears the state and scratch
+ *    regions it lays out), binding another context takes it over and every
+ *    earlier context bound to it then returns FEL_ESTATE, and calls that
+ *    overlap on one GPU (several streams, several threads) race.
+ * Otherwise as fel_bind: FEL_ESTATE if already bound, operators copied on
+ * the given stream (hipStream_t, NULL = default stream). */
+#define FEL_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+FEL_API fel_status fel_bind_static(fel_ctx* ctx, void* hip_stream);
+
 /* Sets the physics of `inst` and initialises its populations to the
  * equilibrium of the given nodal density rho [n], velocity u [n][dim] and
  * pressure p [n], plus the forcing of a pre-streaming collision (whose BGK

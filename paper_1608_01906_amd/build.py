@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfelbm.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("felbm_host.cpp", "felbm_kernels.hip", "felbm_solver.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("felbm_host.cpp", "felbm_kernels.hip", "felbm_solver.hip", "felbm_static.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("felbm_internal.h", "felbm_device.h")] + [
     os.path.join(ROOT, "include", "felbm.h")]
 OBJDIR = os.path.join(HERE, "_build")

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -120,6 +121,7 @@ struct fel_ctx {
     int fbatch[KC_COUNT] = {};
     bool fused_ok = false;
     bool refined = false;  // schedule refined by timing whole solves (refine_schedule)
+    int static_dev = -1;   // device whose static workspace the context is bound to (-1: caller's buffer)
     std::vector<int32_t> fblocks;  // 4 ints per block
     int nfb = 0;
     // profiling
@@ -719,6 +721,9 @@ static fel_status upload_operators(fel_ctx* c) {
     // padding rows of every vector start at zero
     HIP_TRY(c, hipMemsetAsync(c->dev + c->off.psi, 0, c->off.X - c->off.psi, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->dev + c->off.X, 0, c->off.partial - c->off.X, c->stream));
+    // reduction scratch too: a reused workspace (the static one) keeps an earlier context's values
+    HIP_TRY(c, hipMemsetAsync(c->dev + c->off.partial, 0, c->off.fblocks - c->off.partial, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->dev + c->off.fpart0, 0, c->off.status - c->off.fpart0, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return FEL_OK;
 }
@@ -777,14 +782,23 @@ static void set_pointers(fel_ctx* c) {
     L.lap_mode = c->opt.laplacian_mode;
 }
 
-fel_status fel_bind(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
+}  // extern "C"
+
+// Binds the context to the device range [dev_ptr, dev_ptr + bytes): lays
+// out the workspace, uploads the operators and clears the state.  Shared by
+// fel_bind (a caller's buffer) and fel_bind_static (the library's own
+// array); `stat` names the static case in the size error.
+static fel_status bind_range(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream, bool stat) {
     if (!c || !dev_ptr) return FEL_EINVAL;
     if (c->bound) return fail(c, FEL_ESTATE, "already bound");
     if (((uintptr_t)dev_ptr) & 255) return fail(c, FEL_EINVAL, "workspace must be 256-byte aligned");
     fel_status st = plan_layout(c);
     if (st != FEL_OK) return st;
     if (bytes < c->ws_bytes)
-        return fail(c, FEL_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, c->ws_bytes);
+        return fail(c, FEL_ENOMEM, stat ? "the meshes need %2$zu workspace bytes, above the %1$zu bytes of the "
+                                          "static workspace"
+                                        : "workspace of %zu bytes, %zu needed",
+                    bytes, c->ws_bytes);
     c->dev = static_cast<char*>(dev_ptr);
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (c->fused == 2 && !c->fused_ok && c->opt.mass_mode == FEL_MASS_CONSISTENT)
@@ -809,7 +823,57 @@ fel_status fel_bind(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
     return FEL_OK;
 }
 
-}  // extern "C"
+extern "C" fel_status fel_bind(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_stream) {
+    return bind_range(c, dev_ptr, bytes, hip_stream, false);
+}
+
+// ---------------------------------------------------------------------------
+// the static workspace (fel_bind_static, felbm_static.hip)
+
+namespace {
+std::mutex g_static_mu;
+fel_ctx* g_static_owner[fel::kMaxDevices] = {};
+
+// true when the context was bound to a device's static workspace that a
+// later fel_bind_static has taken over
+bool static_stale(fel_ctx* c) {
+    if (c->static_dev < 0) return false;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    return g_static_owner[c->static_dev] != c;
+}
+}  // namespace
+
+#define STATIC_CHECK(c)                                                                                    \
+    do {                                                                                                   \
+        if (static_stale(c))                                                                               \
+            return fail(c, FEL_ESTATE, "the static workspace of device %d was bound to another context", \
+                        (c)->static_dev);                                                                  \
+    } while (0)
+
+fel_status fel::set_error(fel_ctx* c, fel_status st, const char* msg) { return fail(c, st, "%s", msg); }
+
+fel_status fel::bind_static_workspace(fel_ctx* c, void* ptr, size_t bytes, void* hip_stream, int device) {
+    if (!c) return FEL_EINVAL;
+    if (c->bound) return fail(c, FEL_ESTATE, "already bound");
+    // no timing (it creates events and graphs): schedules left open take fixed
+    // defaults, and steps launch directly, with no graph of the library's own
+    for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) {
+        if (!c->batch[k]) c->batch[k] = 2;
+        if (!c->stage[k]) c->stage[k] = 1;
+    }
+    if (c->W >= kQRecurrenceWidth) c->stage[KC_CG_B] = 1;
+    if (!c->fused) c->fused = 1;
+    c->refined = true;
+    fel_status st = bind_range(c, ptr, bytes, hip_stream, true);
+    if (st != FEL_OK) return st;
+    if (c->fused == 2)
+        for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B}) c->fbatch[k] = c->W == 7 ? c->batch[k] : 1;
+    c->use_graph = false;
+    c->static_dev = device;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static_owner[device] = c;
+    return FEL_OK;
+}
 
 // ---------------------------------------------------------------------------
 // launches
@@ -1211,6 +1275,7 @@ fel_status fel_init_fields(fel_ctx* c, int inst, const fel_phys* ph, const doubl
                            const double* p) {
     if (!c || !ph || !rho) return FEL_EINVAL;
     if (!c->bound) return fail(c, FEL_ESTATE, "init_fields before bind");
+    STATIC_CHECK(c);
     if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
     const double drho = ph->rho_l - ph->rho_v;
     if (!(drho > 0.0) || !(ph->rho_v > 0.0) || !(ph->tau_l > 0.0) || !(ph->tau_v > 0.0) || !(ph->dt > 0.0) ||
@@ -1269,6 +1334,7 @@ fel_status fel_init_fields(fel_ctx* c, int inst, const fel_phys* ph, const doubl
 fel_status fel_step(fel_ctx* c, int n_steps) {
     if (!c || n_steps < 0) return FEL_EINVAL;
     if (!c->bound || !all_initialised(c)) return fail(c, FEL_ESTATE, "step before bind/init_fields");
+    STATIC_CHECK(c);
     if (n_steps == 0) return FEL_OK;
     bool untuned = false;
     for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) untuned |= !c->batch[k] || !c->stage[k];
@@ -1322,6 +1388,7 @@ fel_status fel_step(fel_ctx* c, int n_steps) {
 fel_status fel_sync(fel_ctx* c) {
     if (!c) return FEL_EINVAL;
     if (!c->bound) return fail(c, FEL_ESTATE, "sync before bind");
+    STATIC_CHECK(c);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     uint32_t st = 0;
     HIP_TRY(c, hipMemcpy(&st, c->dev + c->off.status, 4, hipMemcpyDeviceToHost));
@@ -1363,6 +1430,7 @@ extern "C" {
 fel_status fel_read_fields(fel_ctx* c, int inst, double* rho, double* u, double* p, double* C) {
     if (!c) return FEL_EINVAL;
     if (!c->bound) return fail(c, FEL_ESTATE, "read before bind");
+    STATIC_CHECK(c);
     if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
     const Instance& I = c->inst[inst];
     if (!I.have_phys) return fail(c, FEL_ESTATE, "instance %d not initialised", inst);
@@ -1387,6 +1455,7 @@ fel_status fel_read_fields(fel_ctx* c, int inst, double* rho, double* u, double*
 fel_status fel_conserved_sums(fel_ctx* c, int inst, double out[6]) {
     if (!c || !out) return FEL_EINVAL;
     if (!c->bound) return fail(c, FEL_ESTATE, "sums before bind");
+    STATIC_CHECK(c);
     if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
     const InstParams& P = c->inst[inst].P;
     if (!c->inst[inst].have_phys) return fail(c, FEL_ESTATE, "instance %d not initialised", inst);
@@ -1402,6 +1471,7 @@ fel_status fel_conserved_sums(fel_ctx* c, int inst, double out[6]) {
 fel_status fel_get_state(fel_ctx* c, int inst, double* psibar) {
     if (!c || !psibar) return FEL_EINVAL;
     if (!c->bound) return fail(c, FEL_ESTATE, "get_state before bind");
+    STATIC_CHECK(c);
     if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const Instance& I = c->inst[inst];
@@ -1445,6 +1515,7 @@ fel_status fel_get_state(fel_ctx* c, int inst, double* psibar) {
 fel_status fel_set_state(fel_ctx* c, int inst, const double* psibar) {
     if (!c || !psibar) return FEL_EINVAL;
     if (!c->bound) return fail(c, FEL_ESTATE, "set_state before bind");
+    STATIC_CHECK(c);
     if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
     if (!c->inst[inst].have_phys) return fail(c, FEL_ESTATE, "set_state needs init_fields first");
     const Instance& I = c->inst[inst];
@@ -1494,6 +1565,7 @@ fel_status fel_set_state(fel_ctx* c, int inst, const double* psibar) {
 fel_status fel_read_aux(fel_ctx* c, int inst, int which, double* out) {
     if (!c || !out) return FEL_EINVAL;
     if (!c->bound) return fail(c, FEL_ESTATE, "read_aux before bind");
+    STATIC_CHECK(c);
     if (inst < 0 || inst >= c->ninst) return fail(c, FEL_EINVAL, "instance %d out of range", inst);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const Instance& I = c->inst[inst];
@@ -1585,6 +1657,10 @@ fel_status fel_tuning(fel_ctx* c, int max_classes, int* n_classes, int* batch, i
 fel_status fel_destroy(fel_ctx* c) {
     if (!c) return FEL_OK;
     if (c->bound && c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+    }
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     for (auto& pe : c->pending) {

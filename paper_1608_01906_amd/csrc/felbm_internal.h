@@ -6,6 +6,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include "../../include/felbm.h"
+
 namespace fel {
 
 // Rows are processed in tiles of TILE rows (one block per tile); every
@@ -159,4 +161,22 @@ hipError_t launch_collide(const DevLayout& L, int tile_begin, int ntiles, hipStr
 hipError_t launch_init(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_sums(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 
+// The static workspace (fel_bind_static): one file-scope device array of
+// kStaticWorkspaceBytes per device, looked up once per device in
+// felbm_static.hip; devices 0..kMaxDevices-1.
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace fel
+
+// Host-side helpers of the static binding (felbm_host.cpp).
+struct fel_ctx;
+namespace fel {
+// Binds ctx to `bytes` bytes of device memory at ptr that the library owns
+// (the static array of `device`): fixes schedules left to timing, runs steps
+// without a graph of its own, and marks ctx as the array's user, which makes
+// every earlier context bound to it report FEL_ESTATE.
+fel_status bind_static_workspace(fel_ctx* c, void* ptr, size_t bytes, void* hip_stream, int device);
+// Records an error message on ctx and returns st.
+fel_status set_error(fel_ctx* c, fel_status st, const char* msg);
 }  // namespace fel

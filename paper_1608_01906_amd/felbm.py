@@ -21,7 +21,7 @@ PREC = {"fp64": 0, "fp32": 1, "fp32_fp16": 2}
 AUX = {"gradrho": 0, "mu": 1, "S": 2, "delta": 3}
 
 # every symbol declared in include/felbm.h
-ABI_SYMBOLS = ["fel_create", "fel_upload_mesh", "fel_workspace_size", "fel_bind", "fel_init_fields",
+ABI_SYMBOLS = ["fel_create", "fel_upload_mesh", "fel_workspace_size", "fel_bind", "fel_bind_static", "fel_init_fields",
                "fel_step", "fel_sync", "fel_read_fields", "fel_conserved_sums", "fel_get_state",
                "fel_set_state", "fel_read_aux", "fel_profile", "fel_profile_read", "fel_layout_info",
                "fel_tuning", "fel_destroy", "fel_last_error", "fel_version"]
@@ -69,6 +69,7 @@ def load_library():
                                     C.POINTER(C.c_int8), _dp, C.POINTER(C.c_uint8), _dp]
     lib.fel_workspace_size.argtypes = [_vp, C.POINTER(C.c_size_t)]
     lib.fel_bind.argtypes = [_vp, _vp, C.c_size_t, _vp]
+    lib.fel_bind_static.argtypes = [_vp, _vp]
     lib.fel_init_fields.argtypes = [_vp, C.c_int, C.POINTER(FelPhys), _dp, _dp, _dp]
     lib.fel_step.argtypes = [_vp, C.c_int]
     lib.fel_sync.argtypes = [_vp]
@@ -175,6 +176,14 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self._check(self.lib.fel_bind(self.h, C.c_void_p(aligned), nbytes, C.c_void_p(self.stream.cuda_stream)),
                     "fel_bind")
+
+    def bind_static(self, device: str = "cuda:0", stream=None):
+        """Binds to the library's static device workspace (no device memory
+        is allocated for the context); `stream` as in bind."""
+        import torch
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self._check(self.lib.fel_bind_static(self.h, C.c_void_p(self.stream.cuda_stream)), "fel_bind_static")
 
     def init_fields(self, inst: int, phys, rho, u=None, p=None):
         rho = np.ascontiguousarray(rho, np.float64)
