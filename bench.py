@@ -204,12 +204,13 @@ def _status(ctx):
     return "ok" if st == felbm.FEL_OK else "FEL_ENOTCONV: CG residual above tolerance"
 
 
-def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="ensemble2d", node_order=0):
+def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="ensemble2d", node_order=0, sched=None):
     import torch
     from paper_1608_01906_amd import felbm
     N = w.n_nodes
     P = 2 * w.lattice
-    ctx = felbm.from_workload(w, precision=precision, device="cuda:0", mass_mode=mass_mode, node_order=node_order)
+    ctx = felbm.from_workload(w, precision=precision, device="cuda:0", mass_mode=mass_mode, node_order=node_order,
+                              **(sched or {}))
     info = ctx.layout_info()
     ctx.step(warmup)
     warm_status = _status(ctx)
@@ -326,7 +327,14 @@ def main():
                     help="mass solve of the headline run: 0 consistent (CG), 1 lumped, 2 consistent (Chebyshev)")
     ap.add_argument("--node-order", type=int, default=0, choices=[0, 1],
                     help="device row order: 0 the workload's node order, 1 Z-order curve")
+    ap.add_argument("--solver-batch", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="fix the solver kernels' population batch (0: tuned)")
+    ap.add_argument("--lds-staging", type=int, default=0, choices=[0, 1, 2],
+                    help="fix the solver kernels' neighbour reads: 1 direct, 2 LDS-staged (0: tuned)")
+    ap.add_argument("--fused", type=int, default=0, choices=[0, 1, 2],
+                    help="fix the CG reductions: 1 finalize launches, 2 fused (0: tuned)")
     args = ap.parse_args()
+    sched = dict(solver_batch=args.solver_batch, lds_staging=args.lds_staging, fused_reductions=args.fused)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -353,7 +361,8 @@ def main():
     print(f"bench: {args.workload}, {len(w.instances)} instances, {N} nodes, {args.precision}, {steps} steps",
           file=sys.stderr, flush=True)
     head, ctx_head = run_gpu(w, args.precision, steps, args.warmup, args.profile_steps,
-                             mass_mode=args.mass_mode, workload=args.workload, node_order=args.node_order)
+                             mass_mode=args.mass_mode, workload=args.workload, node_order=args.node_order,
+                             sched=sched)
     mass = {0: f"consistent, CG x{head['cg_iters']}", 1: "lumped",
             2: f"consistent, Chebyshev x{head['cg_iters']}"}[args.mass_mode]
     out = {

@@ -122,6 +122,10 @@ typedef struct {
                              else fel_bind returns FEL_EINVAL); 0 = chosen by timing both solves on
                              the bound layout before the first step (1 where fused is unavailable).
                              Same results to rounding (the partial sums group rows differently).
+                             The fused kernels' 1024-thread blocks leave 128 registers per thread,
+                             so their population batch is at most 1 for the first kernel of an
+                             iteration, 4 (FP32) / 1 (FP64) for the second and 4 / 2 for the
+                             initial residual; solver_batch above that runs the largest built.
                              The lumped and Chebyshev mass modes reduce nothing: there the option is
                              ignored and fel_tuning reads 1 after the first step */
 } fel_options;
@@ -189,8 +193,15 @@ FEL_API fel_status fel_bind_static(fel_ctx* ctx, void* hip_stream);
 
 /* Sets the physics of `inst` and initialises its populations to the
  * equilibrium of the given nodal density rho [n], velocity u [n][dim] and
- * pressure p [n], plus the forcing of a pre-streaming collision (whose BGK
- * part vanishes at equilibrium).  u or p may be NULL for zero. */
+ * pressure p [n] (the equilibria f_eq = rho Gamma(u) and
+ * g_eq = w p / cs^2 + rho (Gamma(u) - Gamma(0)) of Section 2.1), plus the
+ * forcing of a pre-streaming collision (Section 2.2; its BGK part vanishes
+ * at equilibrium).  The recovered derivatives the forcing needs are those
+ * of Section 2.3.  u or p may be NULL for zero.  May be called again on a
+ * stepped context to restart the instance.  Errors: FEL_EINVAL on a
+ * non-positive or non-finite rho, rho_l <= rho_v, a non-positive tau, dt or
+ * xi, a negative sigma, or an instance out of range; FEL_ESTATE before
+ * fel_bind.  Synchronises the stream. */
 FEL_API fel_status fel_init_fields(fel_ctx* ctx, int inst, const fel_phys* phys, const double* rho,
                                    const double* u, const double* p);
 
@@ -208,15 +219,24 @@ FEL_API fel_status fel_step(fel_ctx* ctx, int n_steps);
  * sync: FEL_ENONFINITE, then FEL_ENOTCONV; clears them. */
 FEL_API fel_status fel_sync(fel_ctx* ctx);
 
-/* Fields of the last step of `inst` (or of its initial state): density,
- * velocity [n][dim], pressure and composition C = (rho - rho_v)/(rho_l - rho_v).
- * Any pointer may be NULL.  Synchronises the stream. */
+/* Fields of the last step of `inst` (or of its initial state), the
+ * moments of the streamed populations (Section 2.2): density rho = sum f,
+ * velocity [n][dim] from rho u = sum e g + dt/2 (S + rho grav), pressure
+ * p = cs^2 sum g + dt/2 cs^2 u . grad rho, and the composition
+ * C = (rho - rho_v)/(rho_l - rho_v) that sets the relaxation time
+ * (Section 2.1).  Any pointer may be NULL; arrays are caller-owned, in the
+ * caller's node order.  Errors: FEL_EINVAL for an instance out of range,
+ * FEL_ESTATE before fel_bind.  Synchronises the stream. */
 FEL_API fel_status fel_read_fields(fel_ctx* ctx, int inst, double* rho, double* u, double* p, double* C);
 
-/* Per-instance FP64 sums over nodes with the lumped mass m as weight:
- * out[0] = sum m rho, out[1] = sum m C, out[2] = sum m (1 - C),
- * out[3..5] = sum m sum_a e_a gbar_a (zero beyond dim), from the stored
- * pre-streaming populations.  Synchronises the stream. */
+/* Per-instance FP64 sums over nodes with the lumped mass m as weight
+ * (the integrals of the P1 fields, Section 2.2.1): out[0] = sum m rho,
+ * out[1] = sum m C, out[2] = sum m (1 - C) (mass of each phase, conserved by
+ * the streaming and collision of Section 2.2 on periodic meshes),
+ * out[3..5] = sum m sum_a e_a gbar_a (momentum; zero beyond dim), from the
+ * stored pre-streaming populations.  out is caller-owned.  Errors:
+ * FEL_EINVAL for an instance out of range, FEL_ESTATE before fel_bind.
+ * Synchronises the stream. */
 FEL_API fel_status fel_conserved_sums(fel_ctx* ctx, int inst, double out[6]);
 
 /* Checkpoint / restart: the stored pre-streaming populations of `inst` as

@@ -867,7 +867,8 @@ fel_status fel::bind_static_workspace(fel_ctx* c, void* ptr, size_t bytes, void*
     fel_status st = bind_range(c, ptr, bytes, hip_stream, true);
     if (st != FEL_OK) return st;
     if (c->fused == 2)
-        for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B}) c->fbatch[k] = c->W == 7 ? c->batch[k] : 1;
+        for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B})
+            c->fbatch[k] = c->W == 7 ? std::min(c->batch[k], fused_max_batch(k, c->opt.precision)) : 1;
     c->use_graph = false;
     c->static_dev = device;
     std::lock_guard<std::mutex> lk(g_static_mu);
@@ -1072,8 +1073,10 @@ fel_status tune_fused_batches(fel_ctx* c) {
     const DevLayout& L = c->L;
     hipStream_t s = c->stream;
     const int tit = L.K > 1 ? 1 : 0;
+    const int prec = c->opt.precision;
     if (c->opt.solver_batch) {
-        for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B}) c->fbatch[cls] = c->W == 7 ? c->opt.solver_batch : 1;
+        for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B})
+            c->fbatch[cls] = c->W == 7 ? std::min(c->opt.solver_batch, fused_max_batch(cls, prec)) : 1;
         return FEL_OK;
     }
     hipEvent_t a = get_event(c), b = get_event(c);
@@ -1083,7 +1086,7 @@ fel_status tune_fused_batches(fel_ctx* c) {
         int best = 0;
         float best_ms = 0.0f;
         for (int t : {1, 2, 4}) {
-            if (c->W != 7 && t != 1) continue;
+            if ((c->W != 7 && t != 1) || t > fused_max_batch(cls, prec)) continue;
             float ms = 0.0f;
             hipError_t e = time_launches(c, a, b, [&] {
                 return cls == KC_CG_INIT ? launch_cg_init_fused(L, t, s)
@@ -1204,7 +1207,7 @@ fel_status refine_schedule(fel_ctx* c) {
             if (!fused && fixed_st && st != fixed_st) continue;
             for (int t : {1, 2, 4}) {
                 if (sb && t != sb) continue;
-                if (fused && c->W != 7 && t != 1) continue;
+                if (fused && ((c->W != 7 && t != 1) || t > fused_max_batch(cls, c->opt.precision))) continue;
                 if (st == 2 && !stage_fits(c, t)) continue;
                 if (t == keep_b && st == keep_s) continue;
                 *bt = t;

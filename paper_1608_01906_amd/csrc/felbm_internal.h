@@ -128,7 +128,9 @@ hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool firs
                        hipStream_t s);
 hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, int it, int batch, bool staged,
                        hipStream_t s);
-// x += sum over the K iterations of alpha_k p_k, in iteration order
+// x = rhs / m + sum over the K iterations of alpha_k p_k, in iteration
+// order, from the stored directions (x is written, never read); with check
+// set it also runs the fused CG's final residual check
 hipError_t launch_cg_x(const DevLayout& L, int tile_begin, int ntiles, bool check, hipStream_t s);
 // op: 0 CG init, 1 alpha, 2 beta, 3 final residual check, 4 conserved sums;
 // nvals values per tile (partials stored population-major)
@@ -140,6 +142,9 @@ hipError_t launch_lumped(const DevLayout& L, int tile_begin, int ntiles, hipStre
 hipError_t launch_cg_init_fused(const DevLayout& L, int batch, hipStream_t s);
 hipError_t launch_cg_a_fused(const DevLayout& L, int it, int batch, hipStream_t s);
 hipError_t launch_cg_b_fused(const DevLayout& L, int it, int batch, hipStream_t s);
+// Largest population batch built for a fused kernel class (KC_CG_INIT,
+// KC_CG_A, KC_CG_B) at a precision: the larger ones would spill registers.
+int fused_max_batch(int cls, int precision);
 // ELL widths from which the CG carries q = M p by its own recurrence (the
 // 3-D layouts, where neighbour gathers dominate): the second CG kernel then
 // reads own rows only and has no staged form.

@@ -594,8 +594,9 @@ __global__ __launch_bounds__(TILE) void k_cheb(DevLayout L, int tile_begin, int 
 // iteration parity in srz (the first block of the instance writes it; the
 // launch reads the other slot), so no block reads what this launch writes.
 // Block partials: cg_init and cg_b write fpart0 (r.z), cg_a writes fpart1
-// (p.q).  One check launch after the last iteration replaces the final
-// residual check of the finalize path.
+// (p.q).  The final residual check of the finalize path is taken by
+// k_cg_x (its check argument) on the last cg_b's partials, with no launch
+// of its own.
 constexpr int FB_THREADS = kFusedTiles * TILE;
 constexpr int FB_WAVES = FB_THREADS / 64;
 
@@ -1273,19 +1274,26 @@ hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {
 }
 
 // Fused kernels: 2-D only (the host enables the path for D2Q9 layouts).
-#define FEL_FUSED_LAUNCH(K, ch, s, ...)                                                                 \
+// Their 1024-thread blocks cap a thread at 128 VGPRs, so only the
+// population batches that fit without spilling are built (fused_max_batch:
+// cg_init 4 in FP32 / 2 in FP64, cg_a 1, cg_b 4 / 1); a larger batch runs
+// as the largest built one.
+#define FEL_FUSED_W7(K, T, B, s, ...) FEL_LAUNCH((K<T, 7, 16, B>), g_, b_, 0, s, __VA_ARGS__)
+#define FEL_FUSED_LAUNCH(K, ch, MAX32, MAX64, s, ...)                                                 \
     do {                                                                                              \
         if (L.Q != 9 || L.nfb <= 0) return hipErrorInvalidValue;                                     \
         const bool f64_ = L.precision == 0;                                                           \
+        const int c_ = min(ch, f64_ ? MAX64 : MAX32);                                                 \
         const dim3 g_(L.nfb), b_(FB_THREADS);                                                         \
         if (L.W == 7) {                                                                               \
-            switch (ch) {                                                                             \
-            case 4: if (f64_) FEL_LAUNCH((K<double, 7, 16, 4>), g_, b_, 0, s, __VA_ARGS__);            \
-                    else FEL_LAUNCH((K<float, 7, 16, 4>), g_, b_, 0, s, __VA_ARGS__); break;          \
-            case 2: if (f64_) FEL_LAUNCH((K<double, 7, 16, 2>), g_, b_, 0, s, __VA_ARGS__);            \
-                    else FEL_LAUNCH((K<float, 7, 16, 2>), g_, b_, 0, s, __VA_ARGS__); break;          \
-            default: if (f64_) FEL_LAUNCH((K<double, 7, 16, 1>), g_, b_, 0, s, __VA_ARGS__);           \
-                     else FEL_LAUNCH((K<float, 7, 16, 1>), g_, b_, 0, s, __VA_ARGS__);                \
+            if (f64_) {                                                                               \
+                if (MAX64 >= 4 && c_ == 4) FEL_FUSED_W7(K, double, (MAX64 >= 4 ? 4 : 1), s, __VA_ARGS__); \
+                else if (MAX64 >= 2 && c_ == 2) FEL_FUSED_W7(K, double, (MAX64 >= 2 ? 2 : 1), s, __VA_ARGS__); \
+                else FEL_FUSED_W7(K, double, 1, s, __VA_ARGS__);                                      \
+            } else {                                                                                  \
+                if (MAX32 >= 4 && c_ == 4) FEL_FUSED_W7(K, float, (MAX32 >= 4 ? 4 : 1), s, __VA_ARGS__); \
+                else if (MAX32 >= 2 && c_ == 2) FEL_FUSED_W7(K, float, (MAX32 >= 2 ? 2 : 1), s, __VA_ARGS__); \
+                else FEL_FUSED_W7(K, float, 1, s, __VA_ARGS__);                                       \
             }                                                                                         \
         } else if (L.W == 12) {                                                                       \
             if (f64_) FEL_LAUNCH((K<double, 12, 16, 1>), g_, b_, 0, s, __VA_ARGS__);                   \
@@ -1295,21 +1303,28 @@ hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {
         }                                                                                             \
     } while (0)
 
+int fused_max_batch(int cls, int precision) {
+    const bool f64 = precision == 0;
+    if (cls == KC_CG_INIT) return f64 ? 2 : 4;
+    if (cls == KC_CG_B) return f64 ? 1 : 4;
+    return 1;
+}
+
 hipError_t launch_cg_init_fused(const DevLayout& L, int batch, hipStream_t s) {
     (void)hipGetLastError();
-    FEL_FUSED_LAUNCH(k_cg_init_fused, batch, s, L);
+    FEL_FUSED_LAUNCH(k_cg_init_fused, batch, 4, 2, s, L);
     return hipGetLastError();
 }
 hipError_t launch_cg_a_fused(const DevLayout& L, int it, int batch, hipStream_t s) {
     (void)hipGetLastError();
     if (it < 0 || it >= L.K) return hipErrorInvalidValue;
-    FEL_FUSED_LAUNCH(k_cg_a_fused, batch, s, L, it);
+    FEL_FUSED_LAUNCH(k_cg_a_fused, batch, 1, 1, s, L, it);
     return hipGetLastError();
 }
 hipError_t launch_cg_b_fused(const DevLayout& L, int it, int batch, hipStream_t s) {
     (void)hipGetLastError();
     if (it < 0 || it >= L.K) return hipErrorInvalidValue;
-    FEL_FUSED_LAUNCH(k_cg_b_fused, batch, s, L, it);
+    FEL_FUSED_LAUNCH(k_cg_b_fused, batch, 4, 1, s, L, it);
     return hipGetLastError();
 }
 
