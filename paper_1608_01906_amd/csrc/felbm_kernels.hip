@@ -69,16 +69,18 @@ __global__ __launch_bounds__(TILE) void k_stream_plain(DevLayout L, int tile_beg
 
 // ---------------------------------------------------------------------------
 // walls + density moment, FP64 populations
-template <int Q>
+// (LAST: the collision, the last reader in the step: non-temporal loads)
+template <int Q, bool LAST = false>
 __device__ __forceinline__ void streamed_plain(const DevLayout& L, int64_t row, int base, double (&v)[Q]) {
     // base = 0 for f, Q for g; X holds Delta for populations 1..Q-1 of each
     const int64_t R = L.R;
     const double* psi = reinterpret_cast<const double*>(L.psi);
     const double* X = reinterpret_cast<const double*>(L.X);
+    auto ld = [](const double* p) { return LAST ? __builtin_nontemporal_load(p) : *p; };
     const int xb = base ? (Q - 1) : 0;
-    v[0] = psi[(int64_t)base * R + row];
+    v[0] = ld(&psi[(int64_t)base * R + row]);
 #pragma unroll
-    for (int a = 1; a < Q; a++) v[a] = psi[(int64_t)(base + a) * R + row] + X[(int64_t)(xb + a - 1) * R + row];
+    for (int a = 1; a < Q; a++) v[a] = ld(&psi[(int64_t)(base + a) * R + row]) + ld(&X[(int64_t)(xb + a - 1) * R + row]);
 }
 
 template <int Q, typename T>
@@ -254,8 +256,8 @@ __global__ __launch_bounds__(TILE) void k_collide_plain(DevLayout L, int tile_be
     const InstParams& P = L.params[L.tile_inst[tile]];
     if (row >= P.row_end) return;
     double f[Q], g[Q];
-    streamed_plain<Q>(L, row, 0, f);
-    streamed_plain<Q>(L, row, Q, g);
+    streamed_plain<Q, true>(L, row, 0, f);
+    streamed_plain<Q, true>(L, row, Q, g);
     const uint32_t mask = L.wmask[row];
     bounce<Q>(mask, f);
     bounce<Q>(mask, g);
@@ -411,10 +413,12 @@ __global__ __launch_bounds__(TILE) void k_stream_dev(DevLayout L, int tile_begin
     // nothing to the sums, so it is skipped
 #pragma unroll
     for (int k = 1; k < W; k++) {
-        const int c = L.col[k * R + row];
+        // pattern and basis values stream through once: non-temporal, so they
+        // do not evict the population rows that neighbouring tiles gather
+        const int c = __builtin_nontemporal_load(&L.col[k * R + row]);
         float b[NB];
 #pragma unroll
-        for (int n = 0; n < NB; n++) b[n] = B[((int64_t)n * W + k) * R + row];
+        for (int n = 0; n < NB; n++) b[n] = __builtin_nontemporal_load(&B[((int64_t)n * W + k) * R + row]);
         const float drf = gat(reff, c) - rf0, drg = gat(refg, c) - rg0;
 #pragma unroll
         for (int a = 1; a < Q; a++) {
@@ -444,17 +448,33 @@ __global__ __launch_bounds__(TILE) void k_stream_dev(DevLayout L, int tile_begin
 
 // streamed deviations e_a = s d_a + Delta_a / w_a of one distribution
 // (base 0: f, base Q: g), walls applied: psi_s,a = w_a (ref + e_a)
-template <int Q, typename S>
+// a stored value as float, non-temporal when NT (FP16 through its bits)
+template <bool NT, typename V>
+__device__ __forceinline__ float ldf(const V* p) {
+    if constexpr (!NT) {
+        return (float)*p;
+    } else if constexpr (std::is_same<V, __half>::value) {
+        const unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p));
+        return __half2float(__ushort_as_half(b));
+    } else {
+        return (float)__builtin_nontemporal_load(p);
+    }
+}
+
+// (LAST: the collision, the last reader of these values in the step, which
+// reads them non-temporally)
+template <int Q, typename S, bool LAST = false>
 __device__ __forceinline__ void streamed_dev(const DevLayout& L, int row, int base, float sc, float (&e)[Q]) {
     using LT = Lat<Q>;
     const int64_t R = L.R;
     const float* X = reinterpret_cast<const float*>(L.X);
+    const S* psi = reinterpret_cast<const S*>(L.psi);
     const int xb = base ? (Q - 1) : 0;
-    e[0] = sc * ldS<S>(L.psi, (int64_t)base * R + row);
+    e[0] = sc * ldf<LAST>(&psi[(int64_t)base * R + row]);
 #pragma unroll
     for (int a = 1; a < Q; a++)
-        e[a] = sc * ldS<S>(L.psi, (int64_t)(base + a) * R + row) +
-               X[(int64_t)(xb + a - 1) * R + row] * (float)(1.0 / LT::w(a));
+        e[a] = sc * ldf<LAST>(&psi[(int64_t)(base + a) * R + row]) +
+               ldf<LAST>(&X[(int64_t)(xb + a - 1) * R + row]) * (float)(1.0 / LT::w(a));
 }
 
 template <int Q, typename S>
@@ -547,8 +567,8 @@ __global__ __launch_bounds__(TILE) void k_collide_dev(DevLayout L, int tile_begi
     if (row >= P.row_end) return;
     const float sc = (float)P.scale, isc = 1.0f / sc;
     float ef[Q], eg[Q];
-    streamed_dev<Q, S>(L, row, 0, sc, ef);
-    streamed_dev<Q, S>(L, row, Q, sc, eg);
+    streamed_dev<Q, S, true>(L, row, 0, sc, ef);
+    streamed_dev<Q, S, true>(L, row, Q, sc, eg);
     const uint32_t mask = L.wmask[row];
     bounce<Q>(mask, ef);
     bounce<Q>(mask, eg);

@@ -391,8 +391,10 @@ __global__ __launch_bounds__(TILE) void k_cg_x(DevLayout L, int tile_begin, int 
         const T* p = ph<T, NP>(L, k);
         const double* al = alpha_of<NP>(L, k, inst);
         T v[NP];
+        // every direction is read here for the last time: non-temporal loads
+        // keep them from displacing data the next kernels reuse
 #pragma unroll
-        for (int j = 0; j < NP; j++) v[j] = p[(int64_t)j * R + row];
+        for (int j = 0; j < NP; j++) v[j] = __builtin_nontemporal_load(&p[(int64_t)j * R + row]);
 #pragma unroll
         for (int j = 0; j < NP; j++) x[j] = x[j] + (T)al[j] * v[j];
     }
