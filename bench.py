@@ -257,13 +257,17 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="ense
         dom_name = solver_kernel_name(dom, precision, info["ell_width"], 2 * (w.lattice - 1), b, sg == 2,
                                       sched.get("fused") == 2)
     sec_step = secs / steps
+    traffic = measured_traffic(workload, precision, mass_mode, dom, dom_name)
     design_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in kern.values()) / prof_steps
     spec = survey_bytes_per_node(D, precision, info["cg_iters"], mass_mode)
     res = dict(value=N * P * steps / secs, ms_per_step=sec_step * 1e3, cg_iters=info["cg_iters"],
                status=status,
                roofline=dict(bound="hbm", kernel=dom, achieved=dk["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                              frac=round(dk["gbs"] / HBM_PEAK_GBS, 4),
-                             traffic=measured_traffic(workload, precision, mass_mode, dom, dom_name),
+                             traffic=traffic,
+                             # measured HBM bytes over the same launch time: the second fraction
+                             traffic_frac=None if traffic is None else
+                             round(traffic / (dk["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                              bytes_per_launch=dk["bytes_per_launch"], avg_launch_us=dk["avg_us"],
                              kernel_instance=dom_name),
                step_bytes_per_node=spec,

@@ -3,16 +3,17 @@
 Error norm: max |x_dev - x_oracle| / max(|x_oracle|_inf, floor_x), with the
 floors of the error-norm reading (the tolerances name no norm): rho -> rho_l,
 C -> 1, p -> the configuration's pressure scale (Laplace jump for drops,
-hydrostatic or dynamic pressure for the channel, rho_l g H for
-Rayleigh-Taylor), u -> its characteristic speed (sqrt(sigma / (rho_l R))
-for drops, the imposed speed for translated drops, the peak of the inflow
-profile for the channel, sqrt(g W) for Rayleigh-Taylor).  The velocity of a
+hydrostatic or dynamic pressure for the channel, the Laplace jump or the
+dynamic pressure for the pipe, rho_l g H for Rayleigh-Taylor), u -> its
+characteristic speed (sqrt(sigma / (rho_l R)) for drops, the imposed speed
+for translated drops, the peak of the inflow profile for the channel and
+the pipe, sqrt(g W) for Rayleigh-Taylor).  The velocity of a
 resting drop is a spurious current, the small residual of forcing terms
 that nearly cancel, so without a floor its relative error is ill posed.
 
 compare_fields also returns "u_rel" = max |u_dev - u_oracle| / max|u_oracle|,
 the velocity error with no floor, which tests report and bound separately
-(see fp32_velocity_bound).
+(see velocity_bound).
 """
 from __future__ import annotations
 
@@ -33,7 +34,7 @@ def characteristic_speed(inst):
         return float(np.linalg.norm(meta["u0"]))
     if kind == "droplet":
         return float(np.sqrt(max(ph.sigma, 1e-12) / (ph.rho_l * meta["radius"])))
-    if kind == "channel":
+    if kind in ("channel", "pipe"):
         return max(float(np.abs(inst.u0).max()), 1e-12)
     g = np.linalg.norm(ph.grav)
     return float(np.sqrt(max(g, 1e-12) * np.ptp(inst.mesh["xyz"][:, 0])))
@@ -49,6 +50,9 @@ def field_floors(inst):
     elif kind == "channel":
         # driven flow: hydrostatic or dynamic pressure, whichever is larger
         p_char = max(ph.rho_l * abs(meta["g"]) * 2 * meta["half_width"], ph.rho_l * u_char ** 2)
+    elif kind == "pipe":
+        # axial flow: the Laplace jump of the cylindrical interface or the dynamic pressure
+        p_char = max(meta["dp_laplace"], ph.rho_l * u_char ** 2)
     else:
         g = np.linalg.norm(ph.grav)
         p_char = ph.rho_l * max(g, 1e-12) * np.ptp(inst.mesh["xyz"][:, 1])
