@@ -43,7 +43,10 @@
  *  - tau uses the composition clamped to [0, 1].
  *  - Walls: natural boundary in the weak form; after streaming, each
  *    population at a wall node pointing into the fluid takes the value of
- *    its opposite (nodal bounce-back).
+ *    its opposite (nodal bounce-back).  A direction points into the fluid
+ *    when e.n > 1e-12 for the wall's inward unit normal n: on a curved wall a
+ *    direction tangential to the wall (e.n = 0) evaluates to a rounding-size
+ *    number of either sign, and is left alone.
  *  - Initial state: equilibrium of the given rho, u, p plus the forcing of
  *    a pre-streaming collision (whose BGK part vanishes there).
  */
@@ -678,7 +681,7 @@ static int one_step(orc *o) {
         for (int a = 0; a < Q; a++) {
             double cn = 0.0;
             for (int r = 0; r < dim; r++) cn += L->e[a][r] * o->wnormal[k * dim + r];
-            if (cn > 0.0) {
+            if (cn > 1e-12) {
                 int b = L->opp[a];
                 o->psibar[(int64_t)a * N + k] = o->psibar[(int64_t)b * N + k];
                 o->psibar[(int64_t)(Q + a) * N + k] = o->psibar[(int64_t)(Q + b) * N + k];

@@ -193,6 +193,81 @@ def delaunay_mesh(dims, *, jitter: float = 0.4, seed: int = 1613) -> dict:
                 wall_normal=np.zeros((n, dim)))
 
 
+def pipe_mesh_3d(radius: float, nz: int, *, jitter: float = 0.2, seed: int = 1614) -> dict:
+    """Circular pipe of the given radius, periodic along z (nz unit layers),
+    with a curved no-slip wall: the setting of the concurrent pipe flow of
+    Section 3.3.
+
+    Cross-section: a centre node and concentric rings k = 1..K (K = round
+    radius) at radius k radius / K, ring k carrying round(2 pi r_k) equally
+    spaced nodes rotated by a seeded angle; the interior rings are jittered
+    radially by +-jitter/2 and angularly by +-jitter/2 of a spacing.  The
+    rings are triangulated by Delaunay (scipy), the triangles extruded
+    through the layers and every prism cut into 3 tetrahedra along the
+    diagonals that run from the lower-numbered vertex of a side face to the
+    higher-numbered one, so the cuts of neighbouring prisms agree.  The
+    outer ring is the wall, with the inward radial unit normal.  The pipe
+    axis sits at (radius, radius).
+    """
+    from scipy.spatial import Delaunay
+    K = int(round(radius))
+    if K < 2 or nz < 2:
+        raise ValueError("pipe needs radius >= 2 and at least 2 layers")
+    pts, wall2 = [np.zeros((1, 2))], [np.zeros(1, np.uint8)]
+    draw = 0
+    for k in range(1, K + 1):
+        rk = k * radius / K
+        m = max(6, int(round(2.0 * np.pi * rk)))
+        th0 = 2.0 * np.pi * uniform01(seed, 1, draw)[0]
+        draw += 1
+        th = th0 + 2.0 * np.pi * np.arange(m) / m
+        r = np.full(m, rk)
+        if k < K and jitter > 0.0:
+            u = uniform01(seed, 2 * m, draw).reshape(m, 2) - 0.5
+            draw += 2 * m
+            r = r + jitter * u[:, 0]
+            th = th + jitter * u[:, 1] * (2.0 * np.pi / m)
+        pts.append(np.stack([r * np.cos(th), r * np.sin(th)], axis=1))
+        wall2.append(np.full(m, 1 if k == K else 0, np.uint8))
+    p2 = np.concatenate(pts)
+    w2 = np.concatenate(wall2)
+    n2 = p2.shape[0]
+    tri = np.sort(Delaunay(p2).simplices, axis=1).astype(np.int64)   # a < b < c
+    # 3 tets per prism, vertices as (2-D index, layer offset)
+    pattern = [((0, 0), (1, 0), (2, 0), (2, 1)),
+               ((0, 0), (1, 0), (1, 1), (2, 1)),
+               ((0, 0), (0, 1), (1, 1), (2, 1))]
+    layers = np.arange(nz, dtype=np.int64)
+    ntri = tri.shape[0]
+    conn = np.empty((3 * ntri * nz, 4), np.int64)
+    shift = np.zeros((3 * ntri * nz, 4, 3), np.int8)
+    L = np.repeat(layers, ntri)
+    T = np.tile(tri, (nz, 1))
+    for t, verts in enumerate(pattern):
+        for a, (v, dl) in enumerate(verts):
+            lay = L + dl
+            conn[t::3, a] = (lay % nz) * n2 + T[:, v]
+            shift[t::3, a, 2] = (lay // nz).astype(np.int8)
+    xyz = np.empty((n2 * nz, 3))
+    xyz[:, 0] = np.tile(p2[:, 0], nz) + radius
+    xyz[:, 1] = np.tile(p2[:, 1], nz) + radius
+    xyz[:, 2] = np.repeat(np.arange(nz, dtype=np.float64), n2)
+    box = np.array([0.0, 0.0, float(nz)])
+    v = xyz[conn] + shift * box
+    vol = np.linalg.det(v[:, 1:, :] - v[:, :1, :])
+    neg = vol < 0
+    conn[neg, 2], conn[neg, 3] = conn[neg, 3].copy(), conn[neg, 2].copy()
+    shift[neg, 2], shift[neg, 3] = shift[neg, 3].copy(), shift[neg, 2].copy()
+    wall = np.tile(w2, nz)
+    normal = np.zeros((n2 * nz, 3))
+    on = wall == 1
+    rr = np.hypot(xyz[on, 0] - radius, xyz[on, 1] - radius)
+    normal[on, 0] = -(xyz[on, 0] - radius) / rr
+    normal[on, 1] = -(xyz[on, 1] - radius) / rr
+    return dict(dim=3, xyz=xyz, conn=conn.astype(np.int32), shift=shift, box=box, wall=wall,
+                wall_normal=normal)
+
+
 def mesh_summary(mesh: dict) -> dict:
     return dict(dim=mesh["dim"], n_nodes=int(mesh["xyz"].shape[0]),
                 n_elems=int(mesh["conn"].shape[0]),
