@@ -268,6 +268,48 @@ def pipe_mesh_3d(radius: float, nz: int, *, jitter: float = 0.2, seed: int = 161
                 wall_normal=normal)
 
 
+def box_mesh(dims, *, jitter: float = 0.2, seed: int = 1615) -> dict:
+    """Closed box with no-slip walls on every side: a unit node grid of shape
+    `dims` (2 or 3 axes), interior nodes jittered by +-jitter per coordinate,
+    each square cut into 2 triangles or each cube into the 6 Kuhn
+    tetrahedra, not periodic.  Wall flags and inward normals come from the
+    boundary facets (inputs.mesh_files), as for a mesh read from a file."""
+    from .mesh_files import _boundary
+    dims = tuple(int(d) for d in dims)
+    dim = len(dims)
+    if dim not in (2, 3) or min(dims) < 2:
+        raise ValueError("need 2 or 3 axes of at least 2 nodes")
+    n = int(np.prod(dims))
+    idx = np.arange(n, dtype=np.int64)
+    coords, rem = [], idx
+    for d in dims[:-1]:
+        rem, r = np.divmod(rem, d)
+        coords.append(r)
+    coords.append(rem)
+    ijk = np.stack(coords, axis=1)
+    xyz = ijk.astype(np.float64)
+    interior = np.all((ijk > 0) & (ijk < np.array(dims) - 1), axis=1)
+    xyz[interior] += _jitter(seed, n, dim, jitter)[interior]
+    cells = ijk[np.all(ijk < np.array(dims) - 1, axis=1)]
+    stride = np.cumprod((1,) + dims[:-1])
+
+    def node(c):
+        return (c * stride).sum(axis=1)
+
+    if dim == 2:
+        corners = [[(0, 0), (1, 0), (1, 1)], [(0, 0), (1, 1), (0, 1)]]
+    else:
+        corners = [[tuple(v) for v in t] for t in _kuhn_corners()]
+    conn = np.concatenate([np.stack([node(cells + np.array(off)) for off in t], axis=1) for t in corners])
+    v = xyz[conn]
+    vol = np.linalg.det(v[:, 1:, :] - v[:, :1, :])
+    neg = vol < 0
+    conn[neg, 0], conn[neg, 1] = conn[neg, 1].copy(), conn[neg, 0].copy()
+    wall, normal = _boundary(xyz, conn, dim)
+    return dict(dim=dim, xyz=xyz, conn=conn.astype(np.int32), shift=np.zeros((conn.shape[0], dim + 1, dim), np.int8),
+                box=np.zeros(dim), wall=wall, wall_normal=normal)
+
+
 def mesh_summary(mesh: dict) -> dict:
     return dict(dim=mesh["dim"], n_nodes=int(mesh["xyz"].shape[0]),
                 n_elems=int(mesh["conn"].shape[0]),

@@ -37,7 +37,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .mesh import grid_mesh_2d, grid_mesh_3d, pipe_mesh_3d, uniform01
+from .mesh import box_mesh, grid_mesh_2d, grid_mesh_3d, pipe_mesh_3d, uniform01
 
 DT_RUN = 0.2
 CS2 = 1.0 / 3.0
@@ -287,6 +287,24 @@ def pipe_profile(r, *, radius, a, rho_w, rho_nw, tau_w, tau_nw, xi, g, dt, sub=6
     outer = np.concatenate([[0.0], np.cumsum(0.5 * (integrand[1:] + integrand[:-1]) * ds)])
     u_of_s = outer[-1] - outer                   # int_s^radius
     return np.interp(r, s, u_of_s)
+
+
+def box_droplet(dims=(48, 48), *, mesh=None, radius=None, rho_l=1.0, rho_v=0.1, sigma=0.01, xi=4.0, tau=0.05,
+                steps=200) -> Workload:
+    """Static drop in the middle of a closed box with no-slip walls on every
+    side: a generated box mesh of node shape `dims`, or any non-periodic
+    mesh dictionary (for instance one read by inputs.mesh_files.read_gmsh).
+    Radius a quarter of the smallest extent by default."""
+    if mesh is None:
+        mesh = box_mesh(dims)
+    lo, hi = mesh["xyz"].min(axis=0), mesh["xyz"].max(axis=0)
+    if radius is None:
+        radius = 0.25 * float((hi - lo).min())
+    inst = droplet_instance(mesh, radius=radius, rho_l=rho_l, rho_v=rho_v, sigma=sigma, xi=xi, tau_l=tau, tau_v=tau,
+                            center=0.5 * (lo + hi))
+    lattice = 9 if mesh["dim"] == 2 else 19
+    return Workload(f"box_droplet_{mesh['xyz'].shape[0]}", lattice, [inst], steps,
+                    "static drop in a closed box with bounce-back walls on every side")
 
 
 PIPE_DT = 0.05
