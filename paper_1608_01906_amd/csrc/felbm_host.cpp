@@ -322,6 +322,7 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
         c->batch[k] = nb;
         c->stage[k] = opt->lds_staging;
     }
+    c->stage[KC_STREAM] = opt->lds_staging;  // the streaming kernel's batch is always 1
     c->fused = opt->fused_reductions;
     *out = c;
     return FEL_OK;
@@ -784,6 +785,10 @@ static void set_pointers(fel_ctx* c) {
 
 }  // extern "C"
 
+namespace {
+bool stream_stage_ok(const fel_ctx* c);
+}  // namespace
+
 // Binds the context to the device range [dev_ptr, dev_ptr + bytes): lays
 // out the workspace, uploads the operators and clears the state.  Shared by
 // fel_bind (a caller's buffer) and fel_bind_static (the library's own
@@ -794,6 +799,8 @@ static fel_status bind_range(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_
     if (((uintptr_t)dev_ptr) & 255) return fail(c, FEL_EINVAL, "workspace must be 256-byte aligned");
     fel_status st = plan_layout(c);
     if (st != FEL_OK) return st;
+    // staging asked of every kernel: the streaming kernel stages where it can
+    if (!stream_stage_ok(c)) c->stage[KC_STREAM] = 1;
     if (bytes < c->ws_bytes)
         return fail(c, FEL_ENOMEM, stat ? "the meshes need %2$zu workspace bytes, above the %1$zu bytes of the "
                                           "static workspace"
@@ -863,6 +870,7 @@ fel_status fel::bind_static_workspace(fel_ctx* c, void* ptr, size_t bytes, void*
     }
     if (c->W >= kQRecurrenceWidth) c->stage[KC_CG_B] = 1;
     if (!c->fused) c->fused = 1;
+    c->stage[KC_STREAM] = 1;
     c->refined = true;
     fel_status st = bind_range(c, ptr, bytes, hip_stream, true);
     if (st != FEL_OK) return st;
@@ -908,6 +916,12 @@ hipError_t timed(fel_ctx* c, int cls, F&& launch) {
 // staged kernel (its dynamic LDS holds 2 ch stage rows of sw values, and a
 // thread stages at most kHaloRounds halo entries).
 bool staged(const fel_ctx* c, int cls) { return c->stage[cls] == 2; }
+// The streaming kernel's staged form: 2-D layouts of ELL width 7 in
+// deviation storage, 2 reference rows and 2 x 2 stage rows of sw floats.
+bool stream_stage_ok(const fel_ctx* c) {
+    return c->opt.lattice == 9 && c->W == 7 && c->opt.precision != 0 && c->hmax <= kHaloRounds * TILE &&
+           6 * (size_t)c->sw * sizeof(float) <= (size_t)kStageBytes;
+}
 bool stage_fits(const fel_ctx* c, int ch) {
     return c->hmax <= kHaloRounds * TILE &&
            2 * (size_t)ch * c->sw * (size_t)elem_size(c->opt.precision) <= (size_t)kStageBytes;
@@ -978,13 +992,29 @@ hipError_t enqueue_solve(fel_ctx* c) {
     return timed(c, KC_CG_X, [&] { return launch_cg_x(L, tb, nt, false, s); });
 }
 
+// Times one launch kind with HIP events: kWarm untimed then kReps timed.
+template <typename F>
+hipError_t time_launches(fel_ctx* c, hipEvent_t a, hipEvent_t b, F&& run, float* ms) {
+    constexpr int kWarm = 2, kReps = 8;
+    (void)hipGetLastError();
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < kWarm && e == hipSuccess; r++) e = run();
+    if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+    for (int r = 0; r < kReps && e == hipSuccess; r++) e = run();
+    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    return e;
+}
+
 // Chooses the schedule of each solver kernel left to the tuner: the
 // population batch (1, 2 or 4: how many populations' loads its pipeline
 // issues ahead, or stages per LDS pass) and direct gathers vs LDS staging,
-// by timing every allowed candidate on the bound layout.  The launches only
-// touch the solve's scratch (X, Rv, Pa, Pb, the stored directions, the
-// alpha history, tile partials), which the next solve rewrites before
-// reading.
+// by timing every allowed candidate on the bound layout; and whether the
+// streaming kernel runs direct or staged, where it has a staged form.  The
+// launches only touch the solve's scratch (X, Rv, Pa, Pb: the streaming
+// kernel's right-hand sides, the stored directions, the alpha history, tile
+// partials), which the next step rewrites before reading.
 fel_status tune_schedule(fel_ctx* c) {
     const DevLayout& L = c->L;
     hipStream_t s = c->stream;
@@ -1012,7 +1042,22 @@ fel_status tune_schedule(fel_ctx* c) {
     }
     constexpr int kWarm = 2, kReps = 8;
     fel_status st = FEL_OK;
+    // the streaming kernel: direct or staged, where the staged form exists
+    if (!stream_stage_ok(c)) c->stage[KC_STREAM] = 1;
+    if (c->stage[KC_STREAM] == 0) {
+        float ms[2] = {0.0f, 0.0f};
+        for (int sg : {1, 2}) {
+            const hipError_t e =
+                time_launches(c, a, b, [&] { return launch_stream(L, 0, nt, sg == 2, s); }, &ms[sg - 1]);
+            if (e != hipSuccess) {
+                st = fail(c, FEL_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e));
+                break;
+            }
+        }
+        c->stage[KC_STREAM] = ms[1] < ms[0] ? 2 : 1;
+    }
     for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) {
+        if (st != FEL_OK) break;
         if (c->batch[cls] != 0 && c->stage[cls] != 0) continue;
         int best_b = 0, best_s = 0;
         float best_ms = 0.0f;
@@ -1050,21 +1095,6 @@ fel_status tune_schedule(fel_ctx* c) {
     c->event_pool.push_back(a);
     c->event_pool.push_back(b);
     return st;
-}
-
-// Times one launch kind with HIP events: kWarm untimed then kReps timed.
-template <typename F>
-hipError_t time_launches(fel_ctx* c, hipEvent_t a, hipEvent_t b, F&& run, float* ms) {
-    constexpr int kWarm = 2, kReps = 8;
-    (void)hipGetLastError();
-    hipError_t e = hipSuccess;
-    for (int r = 0; r < kWarm && e == hipSuccess; r++) e = run();
-    if (e == hipSuccess) e = hipEventRecord(a, c->stream);
-    for (int r = 0; r < kReps && e == hipSuccess; r++) e = run();
-    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(b);
-    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
-    return e;
 }
 
 // Population batches of the fused kernels (1, 2, 4; width 12 only 1), by
@@ -1237,7 +1267,8 @@ hipError_t enqueue_step(fel_ctx* c) {
     hipStream_t s = c->stream;
     const int nt = c->ntiles;
     hipError_t e;
-    if ((e = timed(c, KC_STREAM, [&] { return launch_stream(L, 0, nt, s); })) != hipSuccess) return e;
+    if ((e = timed(c, KC_STREAM, [&] { return launch_stream(L, 0, nt, staged(c, KC_STREAM), s); })) != hipSuccess)
+        return e;
     if ((e = enqueue_solve(c)) != hipSuccess) return e;
     if ((e = timed(c, KC_MOMENTS, [&] { return launch_moments(L, 0, nt, s); })) != hipSuccess) return e;
     if ((e = timed(c, KC_GRAD, [&] { return launch_grad(L, 0, nt, s); })) != hipSuccess) return e;
@@ -1341,6 +1372,7 @@ fel_status fel_step(fel_ctx* c, int n_steps) {
     if (n_steps == 0) return FEL_OK;
     bool untuned = false;
     for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) untuned |= !c->batch[k] || !c->stage[k];
+    untuned |= !c->stage[KC_STREAM];
     if (untuned) {
         fel_status st = tune_schedule(c);
         if (st != FEL_OK) return st;

@@ -118,7 +118,8 @@ extern thread_local LaunchEvents g_launch_events;
 
 // Launchers (felbm_kernels.hip, felbm_solver.hip).  tile_begin/ntiles
 // select the tile range; every launcher returns the hipError_t of the launch.
-hipError_t launch_stream(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
+// staged: the LDS-staged form (2-D, ELL width 7, deviation storage only)
+hipError_t launch_stream(const DevLayout& L, int tile_begin, int ntiles, bool staged, hipStream_t s);
 // The solver launchers take the population batch (1, 2 or 4) of their
 // pipeline or LDS pass and run the LDS-staged kernel when `staged`.
 hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, int batch, bool staged, hipStream_t s);

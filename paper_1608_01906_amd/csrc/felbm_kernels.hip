@@ -449,6 +449,115 @@ __global__ __launch_bounds__(TILE) void k_stream_dev(DevLayout L, int tile_begin
 // streamed deviations e_a = s d_a + Delta_a / w_a of one distribution
 // (base 0: f, base Q: g), walls applied: psi_s,a = w_a (ref + e_a)
 // a stored value as float, non-temporal when NT (FP16 through its bits)
+// The streaming step with neighbour values read from LDS (2-D grids,
+// ELL width 7).  The block stages the two node references at its rows and
+// its halo once, then, one lattice direction a per pass, the stored
+// deviations of f_a and g_a (own rows with coalesced loads, one load per
+// halo entry); every row forms its sums through the 16-bit local columns,
+// slot by slot in the direct kernel's order (the same values and the same
+// operations).  The basis values of the row's slots stay in registers for
+// all directions.  Passes are double-buffered as in the staged solver
+// kernels: the next direction's loads are issued right after the barrier
+// that publishes the current one.  Dynamic LDS: 6 sw floats (references,
+// and 2 buffers of 2 stage rows).  Each thread stages at most HR halo
+// entries (the host checks).
+template <int Q, typename S, int HR>
+__global__ __launch_bounds__(TILE) void k_stream_dev_lds(DevLayout L, int tile_begin) {
+    using LT = Lat<Q>;
+    constexpr int W = 7, NB = LT::NB;
+    static_assert(LT::D == 2, "staged streaming is built for the 2-D lattice");
+    extern __shared__ __align__(16) unsigned char fel_smem[];
+    float* rs = reinterpret_cast<float*>(fel_smem);  // [2][sw] references
+    float* st = rs + 2 * L.sw;                         // [2 buffers][2][sw]
+    const int sw = L.sw;
+    const int tile = tile_begin + tile_of_block(blockIdx.x, gridDim.x);
+    const int64_t R = L.R;
+    const int lr = threadIdx.x;
+    const int row = tile * TILE + lr;
+    const InstParams& P = L.params[L.tile_inst[tile]];
+    const float dt = (float)P.dt, h2 = 0.5f * dt * dt, sc = (float)P.scale;
+    const int hb = L.halo_ptr[tile], hn = L.halo_ptr[tile + 1] - hb;
+    int hg[HR];
+#pragma unroll
+    for (int i = 0; i < HR; i++) {
+        const int h = lr + i * TILE;
+        hg[i] = h < hn ? L.halo_col[hb + h] : -1;
+    }
+    const float* reff = L.ref;
+    const float* refg = L.ref + R;
+    const float rf0 = reff[row], rg0 = refg[row];
+    rs[lr] = rf0;
+    rs[sw + lr] = rg0;
+#pragma unroll
+    for (int i = 0; i < HR; i++) {
+        if (hg[i] >= 0) {
+            rs[TILE + i * TILE + lr] = reff[hg[i]];
+            rs[sw + TILE + i * TILE + lr] = refg[hg[i]];
+        }
+    }
+    // the row's slots: local columns and basis values, read once
+    const float* B = reinterpret_cast<const float*>(L.basis);
+    int lc[W];
+    float b[W][NB];
+#pragma unroll
+    for (int k = 1; k < W; k++) {
+        lc[k] = __builtin_nontemporal_load(&L.lcol[k * R + row]);
+#pragma unroll
+        for (int n = 0; n < NB; n++) b[k][n] = __builtin_nontemporal_load(&B[((int64_t)n * W + k) * R + row]);
+    }
+    float v[2], vh[HR][2];
+    auto fetch = [&](int a) {
+        v[0] = ldS<S>(L.psi, (int64_t)a * R + row);
+        v[1] = ldS<S>(L.psi, (int64_t)(Q + a) * R + row);
+#pragma unroll
+        for (int i = 0; i < HR; i++) {
+            if (hg[i] >= 0) {
+                vh[i][0] = ldS<S>(L.psi, (int64_t)a * R + hg[i]);
+                vh[i][1] = ldS<S>(L.psi, (int64_t)(Q + a) * R + hg[i]);
+            }
+        }
+    };
+    fetch(1);
+    __syncthreads();  // references published
+    float drf[W], drg[W];
+#pragma unroll
+    for (int k = 1; k < W; k++) {
+        drf[k] = rs[lc[k]] - rf0;
+        drg[k] = rs[sw + lc[k]] - rg0;
+    }
+    float* rhs = reinterpret_cast<float*>(L.Pb);
+#pragma unroll
+    for (int a = 1; a < Q; a++) {
+        float* buf = st + ((a - 1) & 1) * 2 * sw;
+        buf[lr] = v[0];
+        buf[sw + lr] = v[1];
+#pragma unroll
+        for (int i = 0; i < HR; i++) {
+            if (hg[i] >= 0) {
+                buf[TILE + i * TILE + lr] = vh[i][0];
+                buf[sw + TILE + i * TILE + lr] = vh[i][1];
+            }
+        }
+        __syncthreads();
+        if (a + 1 < Q) fetch(a + 1);
+        const float ex = LT::e(a, 0), ey = LT::e(a, 1);
+        const float f0 = buf[lr], g0 = buf[sw + lr];
+        float af = 0.0f, ag = 0.0f;
+#pragma unroll
+        for (int k = 1; k < W; k++) {
+            const float coef = dt * (ex * b[k][0] + ey * b[k][1]) +
+                               h2 * (ex * ex * b[k][2] + ey * ey * b[k][3] + ex * ey * b[k][4]);
+            const float df = buf[lc[k]] - f0;
+            const float dg = buf[sw + lc[k]] - g0;
+            af += coef * (drf[k] + sc * df);
+            ag += coef * (drg[k] + sc * dg);
+        }
+        const float w = (float)LT::w(a);
+        rhs[(int64_t)(a - 1) * R + row] = -w * af;
+        rhs[(int64_t)(Q - 1 + a - 1) * R + row] = -w * ag;
+    }
+}
+
 template <bool NT, typename V>
 __device__ __forceinline__ float ldf(const V* p) {
     if constexpr (!NT) {
@@ -694,7 +803,25 @@ __global__ __launch_bounds__(TILE) void k_sums_dev(DevLayout L, int tile_begin) 
 // dispatch
 
 template <int Q, int W> struct StreamBody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, bool staged, hipStream_t s) {
+        if constexpr (Q == 9 && W == 7) {
+            if (staged) {
+                // 2 reference rows and 2 buffers of 2 stage rows
+                const size_t sh = 6 * (size_t)L.sw * sizeof(float);
+                if (L.precision == 0 || L.sw > TILE + kHaloRounds * TILE || sh > (size_t)kStageBytes)
+                    return hipErrorInvalidValue;
+                const bool hr2 = L.sw - TILE <= 2 * TILE;
+                if (L.precision == 1) {
+                    if (hr2) FEL_LAUNCH((k_stream_dev_lds<Q, float, 2>), dim3(nt), dim3(TILE), sh, s, L, tb);
+                    else FEL_LAUNCH((k_stream_dev_lds<Q, float, 4>), dim3(nt), dim3(TILE), sh, s, L, tb);
+                } else {
+                    if (hr2) FEL_LAUNCH((k_stream_dev_lds<Q, __half, 2>), dim3(nt), dim3(TILE), sh, s, L, tb);
+                    else FEL_LAUNCH((k_stream_dev_lds<Q, __half, 4>), dim3(nt), dim3(TILE), sh, s, L, tb);
+                }
+                FEL_CHECK_LAUNCH();
+            }
+        }
+        if (staged) return hipErrorInvalidValue;
         if (L.precision == 0)
             FEL_LAUNCH((k_stream_plain<Q, W>), dim3(nt), dim3(TILE), 0, s, L, tb);
         else if (L.precision == 1)
@@ -769,8 +896,8 @@ template <int Q, int W> struct SumsBody {
     }
 };
 
-hipError_t launch_stream(const DevLayout& L, int tb, int nt, hipStream_t s) {
-    return dispatch_qw<StreamBody>(L, tb, nt, s);
+hipError_t launch_stream(const DevLayout& L, int tb, int nt, bool staged, hipStream_t s) {
+    return dispatch_qw<StreamBody>(L, tb, nt, staged, s);
 }
 hipError_t launch_moments(const DevLayout& L, int tb, int nt, hipStream_t s) {
     return dispatch_qw<MomentsBody>(L, tb, nt, s);

@@ -760,8 +760,10 @@ __device__ __forceinline__ void fused_residual_check(const DevLayout& L, int ins
 // right after the barrier that publishes the current one, so they are in
 // flight while the rows read LDS, and one barrier per pass suffices (a
 // buffer is rewritten two passes later, after every row has passed the
-// intervening barrier).  Each thread stages at most kHaloRounds halo
-// entries (halo <= kHaloRounds * TILE; the host checks).
+// intervening barrier).  Each thread stages at most HR halo entries, HR
+// = 2 when the layout's largest halo is at most 2 TILE, else 4 (halo <=
+// kHaloRounds * TILE; the host checks): the halo registers of the
+// 2-round form leave room for more resident blocks.
 
 template <int W>
 struct LocalCols {
@@ -788,24 +790,25 @@ __device__ __forceinline__ T lds_row_product(const T* mv, const LocalCols<W>& l,
 // own) loads what the row keeps in registers for population j;
 // body.use(j, stage_row, own) finishes the row and returns its dot-product
 // term.  sh holds 2 CH stage rows.
-template <typename T, int NP, int CH, class Body>
+template <typename T, int NP, int CH, int HR, class Body>
 __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int tile, int row, T* sh,
                                            TileReducer<NP>* red) {
+    static_assert(HR >= 1 && HR <= kHaloRounds, "halo rounds out of range");
     static_assert(NP % CH == 0 && NP % RG == 0, "population passes must tile NP");
     const int sw = L.sw;
     const int hb = L.halo_ptr[tile], hn = L.halo_ptr[tile + 1] - hb;
     const int lr = threadIdx.x;
-    int hg[kHaloRounds];
-    T pre_h[kHaloRounds];
+    int hg[HR];
+    T pre_h[HR];
 #pragma unroll
-    for (int i = 0; i < kHaloRounds; i++) {
+    for (int i = 0; i < HR; i++) {
         const int h = lr + i * TILE;
         hg[i] = h < hn ? L.halo_col[hb + h] : -1;
         pre_h[i] = hg[i] >= 0 ? body.pre(hg[i]) : T(0);
     }
     const T pre_own = body.pre(row);
     typename Body::Own own[2][CH];
-    T v[CH], vh[kHaloRounds][CH];
+    T v[CH], vh[HR][CH];
     auto fetch = [&](int j0, typename Body::Own* o) {
 #pragma unroll
         for (int u = 0; u < CH; u++) {
@@ -813,7 +816,7 @@ __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int t
             v[u] = body.stage(j0 + u, row, pre_own);
         }
 #pragma unroll
-        for (int i = 0; i < kHaloRounds; i++) {
+        for (int i = 0; i < HR; i++) {
             if (hg[i] >= 0) {
 #pragma unroll
                 for (int u = 0; u < CH; u++) vh[i][u] = body.stage(j0 + u, hg[i], pre_h[i]);
@@ -829,7 +832,7 @@ __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int t
 #pragma unroll
         for (int u = 0; u < CH; u++) buf[u * sw + lr] = v[u];
 #pragma unroll
-        for (int i = 0; i < kHaloRounds; i++) {
+        for (int i = 0; i < HR; i++) {
             if (hg[i] >= 0) {
 #pragma unroll
                 for (int u = 0; u < CH; u++) buf[u * sw + TILE + i * TILE + lr] = vh[i][u];
@@ -1024,7 +1027,7 @@ __device__ __forceinline__ void staged_row_setup(B& b, const DevLayout& L, int64
     b.row = row;
 }
 
-template <typename T, int W, int NP, int CH>
+template <typename T, int W, int NP, int CH, int HR>
 __global__ __launch_bounds__(TILE) void k_cg_init_lds(DevLayout L, int tile_begin) {
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
@@ -1035,11 +1038,11 @@ __global__ __launch_bounds__(TILE) void k_cg_init_lds(DevLayout L, int tile_begi
     b.rhs = vec<T>(L.Pb);
     b.Rv = vec<T>(L.Rv);
     FEL_REDUCER(red, NP);
-    run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
+    run_staged<T, NP, CH, HR>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
     red.finish(L, tile);
 }
 
-template <typename T, int W, int NP, int CH>
+template <typename T, int W, int NP, int CH, int HR>
 __global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, int first, int it) {
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
@@ -1062,25 +1065,25 @@ __global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, 
         if (first) {
             CgAQStaged<T, W, true> b;
             setup_q(b);
-            run_staged<T, NP, CH>(b, L, tile, row, sh, &red);
+            run_staged<T, NP, CH, HR>(b, L, tile, row, sh, &red);
         } else {
             CgAQStaged<T, W, false> b;
             setup_q(b);
-            run_staged<T, NP, CH>(b, L, tile, row, sh, &red);
+            run_staged<T, NP, CH, HR>(b, L, tile, row, sh, &red);
         }
     } else if (first) {
         CgAStaged<T, W, true> b;
         setup(b);
-        run_staged<T, NP, CH>(b, L, tile, row, sh, &red);
+        run_staged<T, NP, CH, HR>(b, L, tile, row, sh, &red);
     } else {
         CgAStaged<T, W, false> b;
         setup(b);
-        run_staged<T, NP, CH>(b, L, tile, row, sh, &red);
+        run_staged<T, NP, CH, HR>(b, L, tile, row, sh, &red);
     }
     red.finish(L, tile);
 }
 
-template <typename T, int W, int NP, int CH>
+template <typename T, int W, int NP, int CH, int HR>
 __global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, int it) {
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
@@ -1104,12 +1107,12 @@ __global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, 
         b.Pn = ph<T, NP>(L, it);
         b.Rv = vec<T>(L.Rv);
         b.alpha = alpha_of<NP>(L, it, inst);
-        run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
+        run_staged<T, NP, CH, HR>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
     }
     red.finish(L, tile);
 }
 
-template <typename T, int W, int NP, int CH>
+template <typename T, int W, int NP, int CH, int HR>
 __global__ __launch_bounds__(TILE) void k_cheb_first_lds(DevLayout L, int tile_begin, int out0,
                                                          double gamma_d) {
     FEL_ROW_LAYOUT();
@@ -1122,10 +1125,10 @@ __global__ __launch_bounds__(TILE) void k_cheb_first_lds(DevLayout L, int tile_b
     b.x0 = cheb_buf<T>(L, out0);
     b.x1 = cheb_buf<T>(L, 1 - out0);
     b.gamma = (T)gamma_d;
-    run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), (TileReducer<NP>*)nullptr);
+    run_staged<T, NP, CH, HR>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), (TileReducer<NP>*)nullptr);
 }
 
-template <typename T, int W, int NP, int CH>
+template <typename T, int W, int NP, int CH, int HR>
 __global__ __launch_bounds__(TILE) void k_cheb_lds(DevLayout L, int tile_begin, int cur, double omega_d,
                                                    double gamma_d) {
     FEL_ROW_LAYOUT();
@@ -1138,7 +1141,7 @@ __global__ __launch_bounds__(TILE) void k_cheb_lds(DevLayout L, int tile_begin, 
     b.xp = cheb_buf<T>(L, 1 - cur);
     b.omega = (T)omega_d;
     b.gamma = (T)gamma_d;
-    run_staged<T, NP, CH>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), (TileReducer<NP>*)nullptr);
+    run_staged<T, NP, CH, HR>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), (TileReducer<NP>*)nullptr);
 }
 
 // lumped-mass approximation: Delta = rhs / m
@@ -1158,6 +1161,10 @@ __global__ __launch_bounds__(TILE) void k_lumped(DevLayout L, int tile_begin) {
 // dynamic LDS a staged launch may use
 constexpr size_t kMaxStageBytes = kStageBytes;  // plus the static reducer buffer
 
+// halo rounds of the staged instantiation a layout runs (its stage row is
+// TILE plus the largest halo, rounded up to 32)
+inline int staged_halo_rounds(const DevLayout& L) { return L.sw - TILE <= 2 * TILE ? 2 : 4; }
+
 // Launches kernel K<T, W, NP, CH> (or, when staged, K_lds with 2 ch sw
 // values of dynamic LDS) for the context's value type and the population
 // batch ch (1, 2 or 4).
@@ -1170,6 +1177,26 @@ constexpr size_t kMaxStageBytes = kStageBytes;  // plus the static reducer buffe
         }                                                                              \
     } while (0)
 
+// The staged kernels' halo registers are sized for HR rounds of TILE
+// entries: 2 when the layout's largest halo fits (smaller register
+// footprint, more resident blocks), else 4.
+#define FEL_STAGED_LAUNCH_T(K, T, SH, ch, hr, s, nt, ...)                                         \
+    do {                                                                                          \
+        switch (ch) {                                                                             \
+        case 4:                                                                                   \
+            if (hr == 2) FEL_LAUNCH((K<T, W, NP, 4, 2>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); \
+            else FEL_LAUNCH((K<T, W, NP, 4, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);         \
+            break;                                                                                \
+        case 2:                                                                                   \
+            if (hr == 2) FEL_LAUNCH((K<T, W, NP, 2, 2>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); \
+            else FEL_LAUNCH((K<T, W, NP, 2, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);         \
+            break;                                                                                \
+        default:                                                                                  \
+            if (hr == 2) FEL_LAUNCH((K<T, W, NP, 1, 2>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); \
+            else FEL_LAUNCH((K<T, W, NP, 1, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);         \
+        }                                                                                         \
+    } while (0)
+
 #define FEL_SOLVER_LAUNCH(K, ch, staged, s, nt, ...)                                   \
     do {                                                                              \
         const bool f64_ = L.precision == 0;                                           \
@@ -1177,8 +1204,9 @@ constexpr size_t kMaxStageBytes = kStageBytes;  // plus the static reducer buffe
             const size_t sh_ = 2 * (size_t)(ch) * L.sw * (f64_ ? 8 : 4);              \
             if (sh_ > kMaxStageBytes || L.sw > TILE + kHaloRounds * TILE)             \
                 return hipErrorInvalidValue;                                          \
-            if (f64_) FEL_SOLVER_LAUNCH_T(K##_lds, double, sh_, ch, s, nt, __VA_ARGS__); \
-            else FEL_SOLVER_LAUNCH_T(K##_lds, float, sh_, ch, s, nt, __VA_ARGS__);       \
+            const int hr_ = staged_halo_rounds(L);                                    \
+            if (f64_) FEL_STAGED_LAUNCH_T(K##_lds, double, sh_, ch, hr_, s, nt, __VA_ARGS__); \
+            else FEL_STAGED_LAUNCH_T(K##_lds, float, sh_, ch, hr_, s, nt, __VA_ARGS__);       \
         } else {                                                                      \
             if (f64_) FEL_SOLVER_LAUNCH_T(K, double, 0, ch, s, nt, __VA_ARGS__);          \
             else FEL_SOLVER_LAUNCH_T(K, float, 0, ch, s, nt, __VA_ARGS__);                \

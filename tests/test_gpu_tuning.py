@@ -58,6 +58,8 @@ def test_solver_schedules(felbm, oracle_mod, dim, precision, mass_mode, node_ord
             t = ctx.tuning()
             # on 3-D layouts the second CG kernel reads no neighbour values: never staged
             assert all(t[name] == (nb, 1 if (name == "cg_b" and dim == 3) else sg) for name in SOLVER)
+            # the streaming kernel has a staged form for 2-D deviation storage
+            assert t["stream"] == (1, sg if (dim == 2 and precision != "fp64") else 1), t["stream"]
             e = compare_fields(ctx.read_fields(0), o.fields(), inst)
             for k in ("rho", "u", "C"):
                 assert e[k] < tol, (sg, nb, k, e[k])
@@ -81,11 +83,46 @@ def test_tuning_reads_zero_before_first_step(felbm):
     ctx = felbm.from_workload(w, precision="fp32")
     t = ctx.tuning()
     assert all(t[k] == (0, 0) for k in SOLVER)
+    assert t["stream"] == (1, 0)
     ctx.step(1)
     ctx.sync()
     t = ctx.tuning()
     assert t["cheb"] == (1, 1) and t["fused"] in (1, 2)
+    assert t["stream"] in ((1, 1), (1, 2))
     assert all(t[k][0] in (1, 2, 4) and t[k][1] in (1, 2) for k in ("cg_init", "cg_a", "cg_b"))
+
+
+@pytest.mark.parametrize("node_order", [0, 1])
+def test_staged_stream_fp16_storage_vs_oracle(felbm, oracle_mod, node_order):
+    """FP16 deviation storage with every kernel LDS-staged (the streaming
+    kernel's staged form converts the stored FP16 values as the direct one
+    does) and with every kernel direct, against the oracle within the FP16
+    storage bound; the two forms agree to rounding."""
+    from tests._parity import fp16_storage_bound, max_deviation
+    w = _workload(2)
+    inst = w.instances[0]
+    steps = 6
+    o = oracle_mod.Oracle(inst.mesh, w.lattice, inst.phys)
+    o.init(inst.rho0, inst.u0, inst.p0)
+    d0 = max_deviation(o.get_state(), o.fields(), w.lattice)
+    o.step(steps)
+    ref = o.fields()
+    tol = fp16_storage_bound(max(d0, max_deviation(o.get_state(), ref, w.lattice)), inst.phys.rho_l,
+                             inst.phys.rho_v, steps)
+    got = {}
+    for sg in (1, 2):
+        ctx = felbm.from_workload(w, precision="fp32_fp16", lds_staging=sg, node_order=node_order,
+                                  fused_reductions=1)
+        ctx.step(steps)
+        ctx.sync()
+        assert ctx.tuning()["stream"] == (1, sg)
+        got[sg] = ctx.read_fields(0)
+        e = compare_fields(got[sg], ref, inst)
+        print("fp16 storage, staging", sg, {k: f"{v:.2e}" for k, v in e.items()}, "bound", f"{tol:.2e}", flush=True)
+        for k in ("rho", "C"):
+            assert e[k] < tol, (sg, k, e[k], tol)
+    e = compare_fields(got[2], got[1], inst)
+    assert e["rho"] < 1e-5 and e["C"] < 1e-4, e
 
 
 @pytest.mark.parametrize("mass_mode", [0, 2])
