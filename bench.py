@@ -187,18 +187,25 @@ def device_prefix(ctx, workload, steps: int):
     return [ctx.read_fields(i) for i in range(len(workload.instances))]
 
 
-def measured_traffic(workload: str, precision: str, mass_mode: int, kernel: str, name: str | None):
+def traffic_path(workload: str, precision: str, mass_mode: int, node_order: int) -> str:
+    suffix = "_zorder" if node_order == 1 else ""
+    return os.path.join(ROOT, "profiles", f"{workload}_traffic_{precision}_mass{mass_mode}{suffix}.json")
+
+
+def measured_traffic(workload: str, precision: str, mass_mode: int, kernel: str, name: str | None,
+                     node_order: int = 0):
     """HBM bytes per launch of kernel `name` (class `kernel`) from the
-    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by
+    committed rocprofv3 counter summary of the same workload, precision,
+    mass solve and device row order (FETCH_SIZE and WRITE_SIZE scaled by
     their copy-kernel calibration), or None when no summary covers this
     configuration and kernel or the device sources changed since the
     counters were taken."""
     from paper_1608_01906_amd.profiling import device_source_hash, lookup_traffic
-    path = os.path.join(ROOT, "profiles", f"{workload}_traffic_{precision}_mass{mass_mode}.json")
+    path = traffic_path(workload, precision, mass_mode, node_order)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if device_source_hash() != rec["kernel_source_sha256_16"]:
+    if device_source_hash() != rec["kernel_source_sha256_16"] or rec.get("node_order", 0) != node_order:
         return None
     return lookup_traffic(rec, kernel, name)
 
@@ -264,9 +271,9 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="ense
         from paper_1608_01906_amd.profiling import solver_kernel_name
         b, sg = sched[dom]
         dom_name = solver_kernel_name(dom, precision, info["ell_width"], 2 * (w.lattice - 1), b, sg == 2,
-                                      sched.get("fused") == 2)
+                                      sched.get("fused") == 2, info["halo_max"])
     sec_step = secs / steps
-    traffic = measured_traffic(workload, precision, mass_mode, dom, dom_name)
+    traffic = measured_traffic(workload, precision, mass_mode, dom, dom_name, node_order)
     design_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in kern.values()) / prof_steps
     spec = survey_bytes_per_node(D, precision, info["cg_iters"], mass_mode)
     res = dict(value=N * P * steps / secs, ms_per_step=sec_step * 1e3, cg_iters=info["cg_iters"],

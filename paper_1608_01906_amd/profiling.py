@@ -77,17 +77,29 @@ def short_name(name: str) -> str:
     return re.sub(r"\(.*", "", name).replace("void ", "").strip()
 
 
+def staged_halo_rounds(halo_max: int, tile: int = 256) -> int:
+    """Halo rounds of the staged instantiation a layout runs: its stage row
+    holds the tile and the largest halo rounded up to 32; 2 rounds when the
+    halo part fits in 2 tiles, else 4."""
+    sw = (tile + halo_max + 31) // 32 * 32
+    return 2 if sw - tile <= 2 * tile else 4
+
+
 def solver_kernel_name(cls: str, precision: str, W: int, NP: int, batch: int, staged: bool,
-                       fused: bool = False) -> str:
+                       fused: bool = False, halo_max: int = 0) -> str:
     """Short name of the solver kernel a schedule launches (cheb: the
-    iterate kernel, which runs all but the first of each solve)."""
+    iterate kernel, which runs all but the first of each solve); staged
+    kernels carry the halo rounds of the layout (largest halo halo_max)."""
     T = "double" if precision == "fp64" else "float"
-    form = "_fused" if fused and cls in ("cg_init", "cg_a", "cg_b") else ("_lds" if staged else "")
-    return f"fel::k_{cls}{form}<{T}, {W}, {NP}, {batch}>"
+    if fused and cls in ("cg_init", "cg_a", "cg_b"):
+        return f"fel::k_{cls}_fused<{T}, {W}, {NP}, {batch}>"
+    if staged:
+        return f"fel::k_{cls}_lds<{T}, {W}, {NP}, {batch}, {staged_halo_rounds(halo_max)}>"
+    return f"fel::k_{cls}<{T}, {W}, {NP}, {batch}>"
 
 
 def traffic(fetch_csv: str, write_csv: str, copy_mib: float, workload: str, precision: str, mass_mode: int,
-            commands: list[str]) -> dict:
+            commands: list[str], node_order: int = 0) -> dict:
     """Per kernel class and instantiation: dispatches, mean counters and
     calibrated bytes per dispatch.  The autotuner's timing launches of the
     candidate schedules are dispatches of the same kernels on the same
@@ -99,7 +111,7 @@ def traffic(fetch_csv: str, write_csv: str, copy_mib: float, workload: str, prec
     kib = copy_mib * 1024.0
     # the copy reads and writes copy_mib each; use its largest dispatch
     ff, wf = kib / max(fcopy), kib / max(wcopy)
-    out = dict(workload=workload, precision=precision, mass_mode=mass_mode,
+    out = dict(workload=workload, precision=precision, mass_mode=mass_mode, node_order=node_order,
                kernel_source_sha256_16=device_source_hash(), fetch_factor=round(ff, 4), write_factor=round(wf, 4),
                calibration=f"{copy_mib:g} MiB device-to-device copy ({COPY_KERNEL}): FETCH_SIZE {max(fcopy):.1f} "
                            f"KiB, WRITE_SIZE {max(wcopy):.1f} KiB per dispatch for {kib:.0f} KiB moved each way",
@@ -179,6 +191,7 @@ def main():
     t.add_argument("--workload", required=True)
     t.add_argument("--precision", required=True)
     t.add_argument("--mass-mode", type=int, required=True)
+    t.add_argument("--node-order", type=int, default=0, help="device row order of the counted run")
     t.add_argument("--command", action="append", default=[])
     t.add_argument("--out", required=True)
     s = sub.add_parser("stats")
@@ -189,7 +202,8 @@ def main():
     s.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "traffic":
-        rec = traffic(a.fetch_csv, a.write_csv, a.copy_mib, a.workload, a.precision, a.mass_mode, a.command)
+        rec = traffic(a.fetch_csv, a.write_csv, a.copy_mib, a.workload, a.precision, a.mass_mode, a.command,
+                      a.node_order)
         with open(a.out, "w") as f:
             json.dump(rec, f, indent=1)
     else:

@@ -88,7 +88,16 @@ def test_kernel_class(name, cls):
 
 def test_solver_kernel_name():
     assert profiling.solver_kernel_name("cg_b", "fp32", 7, 16, 1, False, True) == "fel::k_cg_b_fused<float, 7, 16, 1>"
-    assert profiling.solver_kernel_name("cg_a", "fp64", 15, 36, 2, True) == "fel::k_cg_a_lds<double, 15, 36, 2>"
+    # staged kernels: 2 halo rounds when the largest halo fits in 2 tiles of 256 rows, else 4
+    assert profiling.solver_kernel_name("cg_a", "fp64", 15, 36, 2, True, halo_max=1024) == \
+        "fel::k_cg_a_lds<double, 15, 36, 2, 4>"
+    assert profiling.solver_kernel_name("cg_a", "fp32", 7, 16, 2, True, halo_max=266) == \
+        "fel::k_cg_a_lds<float, 7, 16, 2, 2>"
+    assert profiling.solver_kernel_name("cg_b", "fp32", 7, 16, 4, True, halo_max=512) == \
+        "fel::k_cg_b_lds<float, 7, 16, 4, 2>"
+    assert profiling.solver_kernel_name("cg_b", "fp32", 7, 16, 4, True, halo_max=516) == \
+        "fel::k_cg_b_lds<float, 7, 16, 4, 4>"
+    assert profiling.solver_kernel_name("cg_a", "fp32", 7, 16, 4, False) == "fel::k_cg_a<float, 7, 16, 4>"
     # the Chebyshev kernels have no fused form
     assert profiling.solver_kernel_name("cheb", "fp32", 7, 16, 2, False, True) == "fel::k_cheb<float, 7, 16, 2>"
 
@@ -147,6 +156,13 @@ def test_measured_traffic_only_for_current_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("channel2d", "fp32", 0, "cg_b", "fel::k_cg_b<float, 7, 16, 2>") == 123
     assert bench.measured_traffic("channel2d", "fp32", 0, "cg_b", "fel::k_cg_b<float, 7, 16, 4>") is None
     assert bench.measured_traffic("channel2d", "fp32", 2, "cg_b", None) is None  # no summary
+    # a summary serves only the device row order it was taken on
+    assert bench.measured_traffic("channel2d", "fp32", 0, "cg_b", "fel::k_cg_b<float, 7, 16, 2>", 1) is None
+    zpath = tmp_path / "profiles" / "channel2d_traffic_fp32_mass0_zorder.json"
+    zpath.write_text(json.dumps(dict(rec, node_order=1)))
+    assert bench.measured_traffic("channel2d", "fp32", 0, "cg_b", "fel::k_cg_b<float, 7, 16, 2>", 1) == 123
+    zpath.write_text(json.dumps(dict(rec, node_order=0)))
+    assert bench.measured_traffic("channel2d", "fp32", 0, "cg_b", "fel::k_cg_b<float, 7, 16, 2>", 1) is None
     rec["kernel_source_sha256_16"] = "0" * 16
     path.write_text(json.dumps(rec))
     assert bench.measured_traffic("channel2d", "fp32", 0, "cg_b", "fel::k_cg_b<float, 7, 16, 2>") is None
