@@ -157,8 +157,19 @@ struct RowOps {
     }
 };
 
-// cg_init: r = rhs - M x0 with x0 = rhs / m, reduces r.z (x0 is formed
-// again by cg_x, from the same operands, so it is not stored here)
+// The residual vector the CG keeps between its kernels: r in the recompute
+// form (2-D layouts), the preconditioned residual z = r / m in the
+// recurrence form (ELL width 15 and up), whose cg_a then needs no inverse
+// masses at the neighbour columns: W registers fewer per thread, which lets
+// the 3-D cg_a run three waves per SIMD instead of two.  (In 2-D the same
+// change made the staged cg_a slower.)
+template <int W>
+constexpr bool z_form() { return W >= kQRecurrenceWidth; }
+
+// cg_init: r = rhs - M x0 with x0 = rhs / m; stores the residual in the
+// layout's form (r, or z = r / m in the recurrence form) and reduces r.z
+// (x0 is formed again by cg_x, from the same operands, so it is not stored
+// here)
 template <typename T, int W>
 struct CgInitRows {
     static constexpr bool kDots = true;
@@ -183,7 +194,7 @@ struct CgInitRows {
         const T res = r.own - acc;
         const int64_t i = (int64_t)j * R + row;
         if (!live) return 0.0;
-        Rv[i] = res;
+        Rv[i] = z_form<W>() ? res * o.mrow : res;
         return (double)res * (double)res * (double)o.mrow;
     }
 };
@@ -274,17 +285,20 @@ struct CgBRows {
 // p_{k-1}, cg_b gathers p_k.  On the 3-D layouts (ELL width 15 and up)
 // gathers dominate, so there q = M p is kept as a vector of its own (in Pa)
 // with the recurrence q = M z + beta q, which is M p in exact arithmetic:
-// cg_a gathers only r, cg_b reads own rows only (q and r).
+// cg_a gathers only z (the form keeps z = r / m, see z_form), cg_b reads
+// own rows only (q and z).
 template <int W>
 constexpr bool q_recurrence() { return W >= kQRecurrenceWidth; }
+static_assert(z_form<15>() == q_recurrence<15>() && z_form<7>() == q_recurrence<7>(),
+              "the recurrence bodies keep z, the recompute bodies r");
 
-// cg_a, recurrence form: z = r / m, p = z + beta p, q = M z + beta q (p, q
-// of the previous iteration unread on the first); reduces p.q -> alpha.
+// cg_a, recurrence form: p = z + beta p, q = M z + beta q (p, q of the
+// previous iteration unread on the first); reduces p.q -> alpha.
 template <typename T, int W, bool FIRST>
 struct CgAQRows {
     static constexpr bool kDots = true;
     struct Regs { T g[W]; T own, p, q; };
-    RowOps<T, W, true> o;
+    RowOps<T, W, false> o;
     const T *Rv, *Pold;
     T *Pnew, *Qv;
     const double* beta;
@@ -305,8 +319,8 @@ struct CgAQRows {
     __device__ __forceinline__ double use(int j, const Regs& r) const {
         T acc = 0;
 #pragma unroll
-        for (int k = 0; k < W; k++) acc += o.mv[k] * (r.g[k] * o.mi[k]);
-        T pn = r.own * o.mrow, qn = acc;
+        for (int k = 0; k < W; k++) acc += o.mv[k] * r.g[k];
+        T pn = r.own, qn = acc;
         if constexpr (!FIRST) {
             const T bet = (T)beta[j];
             pn += bet * r.p;
@@ -319,7 +333,7 @@ struct CgAQRows {
     }
 };
 
-// cg_b, recurrence form: r -= alpha q; reduces r.z -> beta.
+// cg_b, recurrence form: z -= alpha m^-1 q; reduces r.z = m z.z -> beta.
 template <typename T>
 struct CgBQRows {
     static constexpr bool kDots = true;
@@ -337,10 +351,10 @@ struct CgBQRows {
     }
     __device__ __forceinline__ double use(int j, const Regs& r) const {
         const T al = (T)alpha[j];
-        const T res = r.r - al * r.q;
+        const T zn = r.r - al * (r.q * mrow);
         const int64_t i = (int64_t)j * R + row;
-        Rv[i] = res;
-        return (double)res * (double)res * (double)mrow;
+        Rv[i] = zn;
+        return (double)zn * (double)zn * (1.0 / (double)mrow);
     }
 };
 
@@ -870,7 +884,7 @@ struct CgInitStaged {
         const T acc = lds_row_product<T, W>(mv, l, st);
         const T res = o.rhs - acc;
         const int64_t i = (int64_t)j * R + row;
-        Rv[i] = res;
+        Rv[i] = z_form<W>() ? res * mrow : res;
         return (double)res * (double)res * (double)mrow;
     }
 };
@@ -904,8 +918,8 @@ struct CgAStaged {
     }
 };
 
-// cg_a staged, recurrence form: stage z = r / m; p = z + beta p and
-// q = M z + beta q in place.  (The recurrence form's cg_b reads no
+// cg_a staged, recurrence form: stage z; p = z + beta p and q = M z +
+// beta q in place.  (The recurrence form's cg_b reads no
 // neighbour values and has no staged form.)
 template <typename T, int W, bool FIRST>
 struct CgAQStaged {
@@ -918,8 +932,8 @@ struct CgAQStaged {
     const double* beta;
     int64_t R;
     int row;
-    __device__ __forceinline__ T pre(int g) const { return minv[g]; }
-    __device__ __forceinline__ T stage(int j, int g, T mg) const { return Rv[(int64_t)j * R + g] * mg; }
+    __device__ __forceinline__ T pre(int) const { return T(0); }
+    __device__ __forceinline__ T stage(int j, int g, T) const { return Rv[(int64_t)j * R + g]; }
     __device__ __forceinline__ void keep(int j, Own& o) const {
         if constexpr (!FIRST) {
             const int64_t i = (int64_t)j * R + row;
