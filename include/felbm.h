@@ -112,6 +112,9 @@ typedef struct {
                              Staging needs tile halos of at most 1024 rows and two stages of the
                              population batch within 60 KB of LDS; a forced 2 that does not fit makes
                              the first fel_step return FEL_EINVAL (0 then keeps direct gathers).
+                             The option also covers the streaming kernel, whose staged form (one
+                             lattice direction per pass) exists for D2Q9 layouts of ELL width 7 in
+                             FP32 or FP16 storage; elsewhere binding settles it to 1.
                              Every schedule computes the same sums in the same order; results agree
                              to rounding (the staged and direct forms may contract multiply-adds
                              differently) */
@@ -275,10 +278,10 @@ FEL_API fel_status fel_layout_info(fel_ctx* ctx, int64_t* rows, int* ell_width, 
 
 /* Schedule in use for each kernel class k < max_classes (same classes and
  * order as fel_profile_read): population batch and staging (1 direct,
- * 2 LDS-staged); kernels without a tunable schedule read 1; and the CG
- * reduction form (fused_reductions: 1 or 2).  Values left to the tuner
- * (option 0) read 0 until the first fel_step.  batch, staging and fused may
- * be NULL. */
+ * 2 LDS-staged; the streaming kernel's batch is always 1); kernels without
+ * a tunable schedule read 1; and the CG reduction form (fused_reductions:
+ * 1 or 2).  Values left to the tuner (option 0) read 0 until the first
+ * fel_step.  batch, staging and fused may be NULL. */
 FEL_API fel_status fel_tuning(fel_ctx* ctx, int max_classes, int* n_classes, int* batch, int* staging,
                               int* fused);
 
