@@ -8,9 +8,9 @@
 // XCDs receive contiguous tile ranges, so the halo rows a tile gathers were
 // fetched by the same XCD's L2.
 //
-// This file holds the streaming right-hand side, moments, recovery,
-// collision, initialisation and conserved sums; the mass solve is in
-// felbm_solver.hip.  Reductions (conserved sums, CG dot products) are FP64:
+// This file holds the streaming right-hand side (direct, and LDS-staged for
+// 2-D grids), moments, recovery, collision, initialisation and conserved
+// sums; the mass solve is in felbm_solver.hip.  Reductions (conserved sums, CG dot products) are FP64:
 // per-tile partials in a fixed order (wavefront shuffles, then LDS), summed
 // per instance in a fixed order, so results are bitwise reproducible.
 #include "felbm_device.h"
