@@ -270,8 +270,9 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="ense
     if dom in ("cg_init", "cg_a", "cg_b", "cheb"):
         from paper_1608_01906_amd.profiling import solver_kernel_name
         b, sg = sched[dom]
-        dom_name = solver_kernel_name(dom, precision, info["ell_width"], 2 * (w.lattice - 1), b, sg == 2,
-                                      sched.get("fused") == 2, info["halo_max"])
+        dom_name = solver_kernel_name(dom, precision, info["ell_width"], 2 * (w.lattice - 1), b,
+                                      {2: True, 3: "wave"}.get(sg, False), sched.get("fused") == 2,
+                                      info["halo_max"])
     sec_step = secs / steps
     traffic = measured_traffic(workload, precision, mass_mode, dom, dom_name, node_order)
     design_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in kern.values()) / prof_steps
@@ -293,7 +294,7 @@ def run_gpu(w, precision, steps, warmup, prof_steps, mass_mode=0, workload="ense
                step_design_frac=round(design_bytes / sec_step / 1e9 / HBM_PEAK_GBS, 4),
                padded_rows=rows,
                kernels=kern,
-               schedule=dict({k: dict(batch=v[0], staging=("direct", "lds")[v[1] - 1])
+               schedule=dict({k: dict(batch=v[0], staging=("direct", "lds", "lds_wave")[v[1] - 1])
                               for k, v in sched.items() if k in ("stream", "cg_init", "cg_a", "cg_b", "cheb") and k in kern},
                              reductions="fused" if sched.get("fused") == 2 else "finalize launches"),
                halo=dict(max=info["halo_max"], mean=round(info["halo_mean"], 1)),
@@ -352,7 +353,7 @@ def main():
                          "workload's order unless this is given")
     ap.add_argument("--solver-batch", type=int, default=0, choices=[0, 1, 2, 4],
                     help="fix the solver kernels' population batch (0: tuned)")
-    ap.add_argument("--lds-staging", type=int, default=0, choices=[0, 1, 2],
+    ap.add_argument("--lds-staging", type=int, default=0, choices=[0, 1, 2, 3],
                     help="fix the solver kernels' neighbour reads: 1 direct, 2 LDS-staged (0: tuned)")
     ap.add_argument("--fused", type=int, default=0, choices=[0, 1, 2],
                     help="fix the CG reductions: 1 finalize launches, 2 fused (0: tuned)")

@@ -106,15 +106,20 @@ typedef struct {
                              timing on the bound layout before the first step */
     int lds_staging;      /* mass-solve kernels read neighbour values 1 = by direct gathers from
                              memory, 2 = from a per-tile stage in LDS (the tile's rows and its halo
-                             loaded once per population, coalesced), 0 = chosen per kernel by timing.
+                             loaded once per population, coalesced; a block barrier per pass),
+                             3 = from a per-wavefront stage (each 64-row wavefront stages its rows
+                             and its own halo, no barriers; ELL width 7 layouts whose wavefront
+                             halos hold at most 192 columns), 0 = chosen per kernel by timing.
                              On 3-D layouts (ELL width 15 and up) the CG carries M p by its own
                              recurrence: its second kernel reads no neighbour values and runs direct.
-                             Staging needs tile halos of at most 1024 rows and two stages of the
-                             population batch within 60 KB of LDS; a forced 2 that does not fit makes
-                             the first fel_step return FEL_EINVAL (0 then keeps direct gathers).
+                             Staging needs tile halos of at most 1024 rows, two stages of the
+                             population batch within 60 KB of LDS and CG vectors below 2 GiB; a
+                             forced 2 or 3 that does not fit makes the first fel_step return
+                             FEL_EINVAL (0 then keeps direct gathers).
                              The option also covers the streaming kernel, whose staged form (one
-                             lattice direction per pass) exists for D2Q9 layouts of ELL width 7 in
-                             FP32 or FP16 storage; elsewhere binding settles it to 1.
+                             lattice direction per pass, per tile: 3 selects it as 2 does) exists
+                             for D2Q9 layouts of ELL width 7 in FP32 or FP16 storage; elsewhere
+                             binding settles it to 1.
                              Every schedule computes the same sums in the same order; results agree
                              to rounding (the staged and direct forms may contract multiply-adds
                              differently) */
@@ -276,9 +281,27 @@ FEL_API fel_status fel_profile_read(fel_ctx* ctx, int max_classes, int* n_classe
 FEL_API fel_status fel_layout_info(fel_ctx* ctx, int64_t* rows, int* ell_width, int* pops, int* cg_iters,
                                    int* halo_max, double* halo_mean);
 
+/* The LDS staging tables of the layout, before fel_bind (they are freed
+ * there): form 2 = per tile, 3 = per 64-row wavefront of a tile (built for
+ * ELL width 7 layouts whose wavefront halos hold at most 192 columns and
+ * whose schedule may use the form: lds_staging 0 or 3, a mass mode with a
+ * solve).  A list per tile (form 2) or per wavefront (form 3, 4 per tile):
+ * the columns its rows reference outside it, ascending, as device rows.
+ * lcol [ell_width][rows] (row-major by slot, as the device holds it): the
+ * LDS slot each ELL slot reads, < 256 the row's tile-local index, else
+ * 256 + h (form 2) or 256 + 192 w + h (form 3, w the wavefront within the
+ * tile) for entry h of the list.  The device row order is the caller's
+ * unless node_order asks for the curve.  n_lists and n_cols (the length of
+ * list_col) are always written; lcol, list_ptr [n_lists + 1] and list_col
+ * may be NULL.  FEL_ESTATE after binding, FEL_EINVAL for a form the layout
+ * does not have. */
+FEL_API fel_status fel_stage_tables(fel_ctx* ctx, int form, int64_t* n_lists, int64_t* n_cols, uint16_t* lcol,
+                                    int32_t* list_ptr, int32_t* list_col);
+
 /* Schedule in use for each kernel class k < max_classes (same classes and
  * order as fel_profile_read): population batch and staging (1 direct,
- * 2 LDS-staged; the streaming kernel's batch is always 1); kernels without
+ * 2 LDS-staged per tile, 3 per wavefront; the streaming kernel's batch is
+ * always 1); kernels without
  * a tunable schedule read 1; and the CG reduction form (fused_reductions:
  * 1 or 2).  Values left to the tuner (option 0) read 0 until the first
  * fel_step.  batch, staging and fused may be NULL. */

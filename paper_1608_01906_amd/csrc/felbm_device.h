@@ -177,6 +177,41 @@ template <typename T>
 __device__ __forceinline__ T gat(const T* base, int idx) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)idx * (uint32_t)sizeof(T));
 }
+// the store of the same form
+template <typename T>
+__device__ __forceinline__ void sto(T* base, int idx, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)idx * (uint32_t)sizeof(T)) = v;
+}
+
+// A population-major vector [n][R] of T (4 or 8 bytes) through a buffer
+// resource (raw buffer: stride 0, byte offsets).  An access takes the row's
+// byte offset in a VGPR and the population's slice offset (j R sizeof(T),
+// uniform) in an SGPR, so one offset register serves every population of a
+// row and no 64-bit address is formed per access.  The resource covers the
+// whole vector; a row offset at or past its size (kIdleRow) is out of range:
+// the load returns 0 and touches no memory.
+constexpr uint32_t kIdleRow = 0xFFFFFFF0u;
+template <typename T>
+struct BufVec {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit elements");
+    typedef unsigned U2 __attribute__((ext_vector_type(2)));
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ __forceinline__ void bind(const T* base, uint32_t bytes) {
+        rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)bytes, 0x00020000);
+    }
+    __device__ __forceinline__ T load(uint32_t voff, uint32_t soff) const {
+        if constexpr (sizeof(T) == 4)
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+        else
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+    }
+    __device__ __forceinline__ void store(T v, uint32_t voff, uint32_t soff) const {
+        if constexpr (sizeof(T) == 4)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, voff, soff, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), rs, voff, soff, 0);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // dispatch

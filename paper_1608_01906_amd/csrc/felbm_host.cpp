@@ -103,8 +103,14 @@ struct fel_ctx {
     std::vector<uint16_t> lcol;
     int hmax = 0, sw = 0;
     int64_t halo_total = 0;
+    // LDS staging per wavefront (ELL width 7 layouts whose wavefront halos
+    // fit kWaveHaloRounds * 64): halos and local columns, wave_ok when built
+    std::vector<int32_t> whalo_ptr, whalo_col;
+    std::vector<uint16_t> wlcol;
+    int whmax = 0;
+    bool wave_ok = false;
     struct Off {
-        size_t lcol, halo_ptr, halo_col, fblocks, fpart0, fpart1, srz, col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, Ph, rho, grad,
+        size_t lcol, halo_ptr, halo_col, wlcol, whalo_ptr, whalo_col, fblocks, fpart0, fpart1, srz, col, Mval, basis, minv, mlump, wmask, tile_inst, params, psi, ref, X, Rv, Pa, Pb, Ph, rho, grad,
             mu, S, u, p, partial, rz, rz0, alpha, beta, sums, status, end;
     } off{};
     // graph
@@ -112,7 +118,8 @@ struct fel_ctx {
     hipGraphExec_t graph_exec = nullptr;
     bool use_graph = true;
     // schedule of each kernel class: population batch (see run_rows) and
-    // LDS staging (1 direct gathers, 2 staged); 0 = not yet tuned
+    // LDS staging (1 direct gathers, 2 a stage per tile, 3 a stage per
+    // wavefront); 0 = not yet tuned
     int batch[KC_COUNT] = {};
     int stage[KC_COUNT] = {};
     // fused-reduction CG: 0 = not yet chosen, 1 = finalize launches, 2 = fused
@@ -303,7 +310,7 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
     if (opt->node_order != FEL_ORDER_CALLER && opt->node_order != FEL_ORDER_ZCURVE) return FEL_EINVAL;
     const int nb = opt->solver_batch;
     if (nb != 0 && nb != 1 && nb != 2 && nb != 4) return FEL_EINVAL;
-    if (opt->lds_staging < 0 || opt->lds_staging > 2) return FEL_EINVAL;
+    if (opt->lds_staging < 0 || opt->lds_staging > 3) return FEL_EINVAL;
     if (opt->fused_reductions < 0 || opt->fused_reductions > 2) return FEL_EINVAL;
     fel_ctx* c = new (std::nothrow) fel_ctx();
     if (!c) return FEL_ENOMEM;
@@ -322,7 +329,8 @@ fel_status fel_create(const fel_options* opt, fel_ctx** out) {
         c->batch[k] = nb;
         c->stage[k] = opt->lds_staging;
     }
-    c->stage[KC_STREAM] = opt->lds_staging;  // the streaming kernel's batch is always 1
+    // the streaming kernel's batch is always 1; its staged form is per tile
+    c->stage[KC_STREAM] = opt->lds_staging == 3 ? 2 : opt->lds_staging;
     c->fused = opt->fused_reductions;
     *out = c;
     return FEL_OK;
@@ -535,7 +543,79 @@ static void build_halos(fel_ctx* c) {
     }
     c->halo_ptr[nt] = (int32_t)c->halo_col.size();
     c->halo_total = (int64_t)c->halo_col.size();
-    c->sw = (TILE + c->hmax + 31) / 32 * 32;
+    // whole wavefronts of halo entries: a staging wavefront with any entry in
+    // a round writes all 64 of its slots
+    c->sw = (TILE + c->hmax + 63) / 64 * 64;
+}
+
+// The same per 64-row wavefront of a tile (the per-wavefront LDS form):
+// its halo holds every column outside its own 64 rows (rows of the other
+// wavefronts of the tile included), and its slot columns index its own rows
+// by their tile-local position and halo entry h by TILE + w * 3 * 64 + h
+// (w = the wavefront within the tile).  Built for ELL width 7; wave_ok
+// stays false when a wavefront's halo exceeds kWaveHaloRounds * 64.
+static void build_wave_halos(fel_ctx* c) {
+    constexpr int WV = TILE / 64, HW = kWaveHaloRounds * 64;
+    c->wave_ok = false;
+    c->whmax = 0;
+    std::vector<int32_t>().swap(c->whalo_ptr);
+    std::vector<int32_t>().swap(c->whalo_col);
+    std::vector<uint16_t>().swap(c->wlcol);
+    bool wanted = c->opt.mass_mode != FEL_MASS_LUMPED;  // (a schedule left to the tuner or forced to 3)
+    bool any = false;
+    for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) any |= c->stage[k] == 0 || c->stage[k] == 3;
+    if (c->W != 7 || !wanted || !any) return;
+    const int64_t R = c->R;
+    const int W = c->W, nw = c->ntiles * WV;
+    std::vector<int32_t> ptr(nw + 1, 0), hcol;
+    std::vector<uint16_t> wl((size_t)W * R);
+    for (int64_t r = 0; r < R; r++)
+        for (int k = 0; k < W; k++) wl[k * R + r] = (uint16_t)(r % TILE);
+    std::vector<int32_t> cols;
+    for (int w = 0; w < nw; w++) {
+        ptr[w] = (int32_t)hcol.size();
+        const int t = w / WV;
+        const Instance& I = c->inst[c->tile_inst[t]];
+        const HostMesh& hm = I.mesh;
+        const int64_t rb = I.P.row_begin, w0 = (int64_t)w * 64, t0 = (int64_t)t * TILE;
+        cols.clear();
+        for (int64_t r = w0; r < w0 + 64; r++) {
+            const int64_t k = r - rb;
+            if (k >= hm.N) continue;
+            for (int sl = 0; sl < hm.W; sl++) {
+                const int32_t cl = hm.col[k * hm.W + sl];
+                if (cl < 0) continue;
+                const int64_t g = rb + cl;
+                if (g < w0 || g >= w0 + 64) cols.push_back((int32_t)g);
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        c->whmax = std::max(c->whmax, (int)cols.size());
+        if ((int)cols.size() > HW) return;  // no per-wavefront form for this layout
+        const int slot0 = TILE + (w % WV) * HW;
+        for (int64_t r = w0; r < w0 + 64; r++) {
+            const int64_t k = r - rb;
+            if (k >= hm.N) continue;
+            for (int sl = 0; sl < hm.W; sl++) {
+                const int32_t cl = hm.col[k * hm.W + sl];
+                if (cl < 0) continue;
+                const int64_t g = rb + cl;
+                int loc;
+                if (g >= w0 && g < w0 + 64)
+                    loc = (int)(g - t0);
+                else
+                    loc = slot0 + (int)(std::lower_bound(cols.begin(), cols.end(), (int32_t)g) - cols.begin());
+                wl[sl * R + r] = (uint16_t)loc;
+            }
+        }
+        hcol.insert(hcol.end(), cols.begin(), cols.end());
+    }
+    ptr[nw] = (int32_t)hcol.size();
+    c->whalo_ptr.swap(ptr);
+    c->whalo_col.swap(hcol);
+    c->wlcol.swap(wl);
+    c->wave_ok = true;
 }
 
 // Blocks of the fused-reduction CG: each instance's tiles in groups of
@@ -603,6 +683,7 @@ static fel_status plan_layout(fel_ctx* c) {
     c->R = rows;
     c->ntiles = (int)(rows / TILE);
     build_halos(c);
+    build_wave_halos(c);
     build_fused_blocks(c);
     const size_t R = (size_t)rows;
     const int W = c->W, NB = c->NB, NP = c->NP, Q = c->opt.lattice, D = c->lat.D;
@@ -618,6 +699,9 @@ static fel_status plan_layout(fel_ctx* c) {
     f.lcol = take(2 * W * R);
     f.halo_ptr = take(4 * ((size_t)c->ntiles + 1));
     f.halo_col = take(4 * std::max<size_t>(c->halo_col.size(), 1));
+    f.wlcol = take(2 * c->wlcol.size());
+    f.whalo_ptr = take(4 * c->whalo_ptr.size());
+    f.whalo_col = take(4 * c->whalo_col.size());
     f.col = take(4 * W * R);
     f.Mval = take(s * W * R);
     f.basis = take(s * NB * W * R);
@@ -711,6 +795,11 @@ static fel_status upload_operators(fel_ctx* c) {
     HIP_TRY(c, put(c->off.lcol, c->lcol.data(), c->lcol.size() * 2));
     HIP_TRY(c, put(c->off.halo_ptr, c->halo_ptr.data(), c->halo_ptr.size() * 4));
     if (!c->halo_col.empty()) HIP_TRY(c, put(c->off.halo_col, c->halo_col.data(), c->halo_col.size() * 4));
+    if (c->wave_ok) {
+        HIP_TRY(c, put(c->off.wlcol, c->wlcol.data(), c->wlcol.size() * 2));
+        HIP_TRY(c, put(c->off.whalo_ptr, c->whalo_ptr.data(), c->whalo_ptr.size() * 4));
+        if (!c->whalo_col.empty()) HIP_TRY(c, put(c->off.whalo_col, c->whalo_col.data(), c->whalo_col.size() * 4));
+    }
     HIP_TRY(c, put_t(c->off.Mval, Mv));
     HIP_TRY(c, put_t(c->off.basis, basis));
     HIP_TRY(c, put_t(c->off.minv, minv));
@@ -746,6 +835,9 @@ static void set_pointers(fel_ctx* c) {
     L.halo_ptr = reinterpret_cast<const int32_t*>(d + f.halo_ptr);
     L.halo_col = reinterpret_cast<const int32_t*>(d + f.halo_col);
     L.sw = c->sw;
+    L.wlcol = c->wave_ok ? reinterpret_cast<const uint16_t*>(d + f.wlcol) : nullptr;
+    L.whalo_ptr = c->wave_ok ? reinterpret_cast<const int32_t*>(d + f.whalo_ptr) : nullptr;
+    L.whalo_col = c->wave_ok ? reinterpret_cast<const int32_t*>(d + f.whalo_col) : nullptr;
     L.Mval = d + f.Mval;
     L.basis = d + f.basis;
     L.minv = d + f.minv;
@@ -824,6 +916,9 @@ static fel_status bind_range(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_
     }
     std::vector<uint16_t>().swap(c->lcol);
     std::vector<int32_t>().swap(c->halo_col);
+    std::vector<uint16_t>().swap(c->wlcol);
+    std::vector<int32_t>().swap(c->whalo_ptr);
+    std::vector<int32_t>().swap(c->whalo_col);
     c->bound = true;
     // graphs cannot be captured on the legacy default stream
     c->use_graph = c->stream != nullptr;
@@ -922,9 +1017,12 @@ bool stream_stage_ok(const fel_ctx* c) {
     return c->opt.lattice == 9 && c->W == 7 && c->opt.precision != 0 && c->hmax <= kHaloRounds * TILE &&
            6 * (size_t)c->sw * sizeof(float) <= (size_t)kStageBytes;
 }
-bool stage_fits(const fel_ctx* c, int ch) {
-    return c->hmax <= kHaloRounds * TILE &&
-           2 * (size_t)ch * c->sw * (size_t)elem_size(c->opt.precision) <= (size_t)kStageBytes;
+// stage 2 per tile, 3 per wavefront
+bool stage_fits(const fel_ctx* c, int ch, int stage) {
+    const size_t row = stage == 3 ? (size_t)kWaveStageWidth : (size_t)c->sw;
+    return (stage == 3 ? c->wave_ok : c->hmax <= kHaloRounds * TILE) &&
+           staged_vectors_fit(c->NP, c->R, c->opt.precision) &&
+           2 * (size_t)ch * row * (size_t)elem_size(c->opt.precision) <= (size_t)kStageBytes;
 }
 
 hipError_t enqueue_solve(fel_ctx* c) {
@@ -938,7 +1036,7 @@ hipError_t enqueue_solve(fel_ctx* c) {
         const double a = 1.0 / (c->lat.D + 2), b = 1.0;
         const double theta = 0.5 * (b + a), sigma = (b - a) / (b + a), gamma = 1.0 / theta;
         const int K = c->cg_iters, ch = c->batch[KC_CHEB];
-        const bool st = staged(c, KC_CHEB);
+        const int st = c->stage[KC_CHEB];
         const int out0 = (K % 2 == 0) ? 0 : 1;  // x_K must land in buffer 0 (X)
         if ((e = timed(c, KC_CHEB, [&] { return launch_cheb_first(L, tb, nt, out0, gamma, ch, st, s); })) != hipSuccess)
             return e;
@@ -973,18 +1071,18 @@ hipError_t enqueue_solve(fel_ctx* c) {
         return timed(c, KC_FINALIZE, [&] { return launch_finalize(L, 0, ni, op, np, s, it); });
     };
     if ((e = timed(c, KC_CG_INIT, [&] {
-             return launch_cg_init(L, tb, nt, c->batch[KC_CG_INIT], staged(c, KC_CG_INIT), s);
+             return launch_cg_init(L, tb, nt, c->batch[KC_CG_INIT], c->stage[KC_CG_INIT], s);
          })) != hipSuccess)
         return e;
     if ((e = fin(0)) != hipSuccess) return e;
     for (int it = 0; it < c->cg_iters; it++) {
         if ((e = timed(c, KC_CG_A, [&] {
-                 return launch_cg_a(L, tb, nt, it == 0, it, c->batch[KC_CG_A], staged(c, KC_CG_A), s);
+                 return launch_cg_a(L, tb, nt, it == 0, it, c->batch[KC_CG_A], c->stage[KC_CG_A], s);
              })) != hipSuccess)
             return e;
         if ((e = fin(1, it)) != hipSuccess) return e;
         if ((e = timed(c, KC_CG_B, [&] {
-                 return launch_cg_b(L, tb, nt, it, c->batch[KC_CG_B], staged(c, KC_CG_B), s);
+                 return launch_cg_b(L, tb, nt, it, c->batch[KC_CG_B], c->stage[KC_CG_B], s);
              })) != hipSuccess)
             return e;
         if ((e = fin(it == c->cg_iters - 1 ? 3 : 2)) != hipSuccess) return e;
@@ -1009,7 +1107,8 @@ hipError_t time_launches(fel_ctx* c, hipEvent_t a, hipEvent_t b, F&& run, float*
 
 // Chooses the schedule of each solver kernel left to the tuner: the
 // population batch (1, 2 or 4: how many populations' loads its pipeline
-// issues ahead, or stages per LDS pass) and direct gathers vs LDS staging,
+// issues ahead, or stages per LDS pass) and direct gathers vs LDS staging
+// per tile (block barriers) vs per wavefront (no barriers, larger halos),
 // by timing every allowed candidate on the bound layout; and whether the
 // streaming kernel runs direct or staged, where it has a staged form.  The
 // launches only touch the solve's scratch (X, Rv, Pa, Pb: the streaming
@@ -1023,7 +1122,7 @@ fel_status tune_schedule(fel_ctx* c) {
     const double gamma = 2.0 / (1.0 + 1.0 / (c->lat.D + 2));
     hipEvent_t a = get_event(c), b = get_event(c);
     if (!a || !b) return fail(c, FEL_EDEVICE, "event creation failed");
-    auto run = [&](int cls, int t, bool st) -> hipError_t {
+    auto run = [&](int cls, int t, int st) -> hipError_t {
         switch (cls) {
             case KC_CG_INIT: return launch_cg_init(L, 0, nt, t, st, s);
             case KC_CG_A: return launch_cg_a(L, 0, nt, tit == 0, tit, t, st, s);
@@ -1061,16 +1160,16 @@ fel_status tune_schedule(fel_ctx* c) {
         if (c->batch[cls] != 0 && c->stage[cls] != 0) continue;
         int best_b = 0, best_s = 0;
         float best_ms = 0.0f;
-        for (int sg : {1, 2}) {
+        for (int sg : {1, 2, 3}) {
             if (c->stage[cls] != 0 && c->stage[cls] != sg) continue;
             for (int t : {1, 2, 4}) {
                 if (c->batch[cls] != 0 && c->batch[cls] != t) continue;
-                if (sg == 2 && !stage_fits(c, t)) continue;
+                if (sg >= 2 && !stage_fits(c, t, sg)) continue;
                 (void)hipGetLastError();
                 hipError_t e = hipSuccess;
-                for (int r = 0; r < kWarm && e == hipSuccess; r++) e = run(cls, t, sg == 2);
+                for (int r = 0; r < kWarm && e == hipSuccess; r++) e = run(cls, t, sg);
                 if (e == hipSuccess) e = hipEventRecord(a, s);
-                for (int r = 0; r < kReps && e == hipSuccess; r++) e = run(cls, t, sg == 2);
+                for (int r = 0; r < kReps && e == hipSuccess; r++) e = run(cls, t, sg);
                 if (e == hipSuccess) e = hipEventRecord(b, s);
                 if (e == hipSuccess) e = hipEventSynchronize(b);
                 float ms = 0.0f;
@@ -1085,8 +1184,12 @@ fel_status tune_schedule(fel_ctx* c) {
         }
         if (st != FEL_OK) break;
         if (best_b == 0) {  // a fixed staged batch whose stage does not fit
-            st = fail(c, FEL_EINVAL, "LDS stage of 2 x %d rows of %d values (halo %d) does not fit",
-                      c->batch[cls], c->sw, c->hmax);
+            if (c->stage[cls] == 3)
+                st = fail(c, FEL_EINVAL, "no per-wavefront LDS stage of batch %d (wavefront halo %d, ELL width %d)",
+                          c->batch[cls], c->whmax, c->W);
+            else
+                st = fail(c, FEL_EINVAL, "LDS stage of 2 x %d rows of %d values (halo %d) does not fit",
+                          c->batch[cls], c->sw, c->hmax);
             break;
         }
         c->batch[cls] = best_b;
@@ -1232,13 +1335,13 @@ fel_status refine_schedule(fel_ctx* c) {
         float best = cur;
         // the recurrence form's cg_b has no staged form
         const int fixed_st = (cls == KC_CG_B && c->W >= kQRecurrenceWidth) ? 1 : ls;
-        for (int st : {1, 2}) {
-            if (fused && st == 2) continue;  // the fused kernels gather directly
+        for (int st : {1, 2, 3}) {
+            if (fused && st >= 2) continue;  // the fused kernels gather directly
             if (!fused && fixed_st && st != fixed_st) continue;
             for (int t : {1, 2, 4}) {
                 if (sb && t != sb) continue;
                 if (fused && ((c->W != 7 && t != 1) || t > fused_max_batch(cls, c->opt.precision))) continue;
-                if (st == 2 && !stage_fits(c, t)) continue;
+                if (st >= 2 && !stage_fits(c, t, st)) continue;
                 if (t == keep_b && st == keep_s) continue;
                 *bt = t;
                 if (sg) *sg = st;
@@ -1370,6 +1473,15 @@ fel_status fel_step(fel_ctx* c, int n_steps) {
     if (!c->bound || !all_initialised(c)) return fail(c, FEL_ESTATE, "step before bind/init_fields");
     STATIC_CHECK(c);
     if (n_steps == 0) return FEL_OK;
+    // a staged schedule the options fix completely but the layout cannot run
+    for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) {
+        const int mode = c->opt.mass_mode;
+        const bool used = cls == KC_CHEB ? mode == FEL_MASS_CHEBYSHEV : (mode == FEL_MASS_CONSISTENT && c->fused != 2);
+        if (used && c->batch[cls] && c->stage[cls] >= 2 && !stage_fits(c, c->batch[cls], c->stage[cls]))
+            return fail(c, FEL_EINVAL, "%s LDS stage (form %d, batch %d) does not fit this layout (halo %d, "
+                        "wavefront halo %d, ELL width %d)", kernel_class_name(cls), c->stage[cls], c->batch[cls],
+                        c->hmax, c->whmax, c->W);
+    }
     bool untuned = false;
     for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB}) untuned |= !c->batch[k] || !c->stage[k];
     untuned |= !c->stage[KC_STREAM];
@@ -1673,6 +1785,26 @@ fel_status fel_layout_info(fel_ctx* c, int64_t* rows, int* ell_width, int* pops,
     if (cg_iters) *cg_iters = c->opt.mass_mode == FEL_MASS_LUMPED ? 0 : c->cg_iters;
     if (halo_max) *halo_max = c->hmax;
     if (halo_mean) *halo_mean = c->ntiles ? (double)c->halo_total / c->ntiles : 0.0;
+    return FEL_OK;
+}
+
+fel_status fel_stage_tables(fel_ctx* c, int form, int64_t* n_lists, int64_t* n_cols, uint16_t* lcol,
+                            int32_t* list_ptr, int32_t* list_col) {
+    if (!c || !n_lists || !n_cols || (form != 2 && form != 3)) return FEL_EINVAL;
+    if (c->bound) return fail(c, FEL_ESTATE, "the staging tables are freed at binding");
+    fel_status st = plan_layout(c);
+    if (st != FEL_OK) return st;
+    if (form == 3 && !c->wave_ok)
+        return fail(c, FEL_EINVAL, "no per-wavefront staging (ELL width %d, largest wavefront halo %d)", c->W,
+                    c->whmax);
+    const auto& lc = form == 3 ? c->wlcol : c->lcol;
+    const auto& ptr = form == 3 ? c->whalo_ptr : c->halo_ptr;
+    const auto& col = form == 3 ? c->whalo_col : c->halo_col;
+    *n_lists = (int64_t)ptr.size() - 1;
+    *n_cols = (int64_t)col.size();
+    if (lcol) std::copy(lc.begin(), lc.end(), lcol);
+    if (list_ptr) std::copy(ptr.begin(), ptr.end(), list_ptr);
+    if (list_col) std::copy(col.begin(), col.end(), list_col);
     return FEL_OK;
 }
 

@@ -47,7 +47,16 @@ struct DevLayout {
     const uint16_t* lcol;       // [W][R]
     const int32_t* halo_ptr;    // [ntiles + 1]
     const int32_t* halo_col;    // [halo_ptr[ntiles]]
-    int sw;                     // TILE + largest halo, rounded up to 32
+    int sw;                     // TILE + largest halo, rounded up to 64
+    // LDS staging per wavefront (staging form 3; null where the layout has
+    // none): each 64-row wavefront of a tile stages its own rows and its
+    // own halo (columns outside those 64 rows, ascending, at most
+    // kWaveHaloRounds * 64); slot columns < TILE are the row's tile-local
+    // index (a row of the same wavefront), TILE + w kWaveHaloRounds 64 + h
+    // is halo entry h of wavefront w of the tile
+    const uint16_t* wlcol;      // [W][R]
+    const int32_t* whalo_ptr;   // [4 ntiles + 1]
+    const int32_t* whalo_col;   // [whalo_ptr[4 ntiles]]
     const int32_t* tile_inst;   // [ntiles]
     const InstParams* params;   // [ninst]
     // populations
@@ -121,13 +130,15 @@ extern thread_local LaunchEvents g_launch_events;
 // staged: the LDS-staged form (2-D, ELL width 7, deviation storage only)
 hipError_t launch_stream(const DevLayout& L, int tile_begin, int ntiles, bool staged, hipStream_t s);
 // The solver launchers take the population batch (1, 2 or 4) of their
-// pipeline or LDS pass and run the LDS-staged kernel when `staged`.
-hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, int batch, bool staged, hipStream_t s);
+// pipeline or LDS pass and the staging form: 1 direct gathers, 2 a stage
+// per tile, 3 a stage per wavefront (ELL width 7 layouts with wavefront
+// halos, wlcol set).
+hipError_t launch_cg_init(const DevLayout& L, int tile_begin, int ntiles, int batch, int stage, hipStream_t s);
 // it = CG iteration: p_it is written to (cg_a) and read from (cg_b) slice
 // it of Ph, alpha_it to slice it of alpha.
-hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, int it, int batch, bool staged,
+hipError_t launch_cg_a(const DevLayout& L, int tile_begin, int ntiles, bool first, int it, int batch, int stage,
                        hipStream_t s);
-hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, int it, int batch, bool staged,
+hipError_t launch_cg_b(const DevLayout& L, int tile_begin, int ntiles, int it, int batch, int stage,
                        hipStream_t s);
 // x = rhs / m + sum over the K iterations of alpha_k p_k, in iteration
 // order, from the stored directions (x is written, never read); with check
@@ -151,15 +162,26 @@ int fused_max_batch(int cls, int precision);
 // reads own rows only and has no staged form.
 constexpr int kQRecurrenceWidth = 15;
 constexpr int kHaloRounds = 4;       // LDS staging: halo entries per thread at most (halo <= 4 TILE)
+// LDS staging per wavefront: halo entries per lane at most (a wavefront's
+// halo <= 192), and the stage row: the tile's rows, then 3 x 64 halo slots
+// for each of its 4 wavefronts
+constexpr int kWaveHaloRounds = 3;
+constexpr int kWaveStageWidth = TILE + (TILE / 64) * kWaveHaloRounds * 64;
+// The staged solver kernels address a [2(Q-1)][R] vector through one buffer
+// resource with 32-bit byte offsets: its size must stay below 2 GiB (larger
+// layouts run the direct kernels).
+inline bool staged_vectors_fit(int np, int64_t R, int precision) {
+    return (int64_t)np * R * (precision == 0 ? 8 : 4) < ((int64_t)1 << 31);
+}
 constexpr int kStageBytes = 60 * 1024;  // LDS staging: dynamic LDS per block at most (2 batches of sw rows)
 constexpr int kFusedTiles = 4;       // tiles per fused-reduction block
 constexpr int kFusedMaxBlocks = 256; // per instance (a lane of a fused block loads at most 4 of its partials)
 // Chebyshev solve: first launch writes x_0 to buffer out0 and x_1 to the
 // other (0 = X, 1 = Pa); each later launch reads x_k from buffer cur.
 hipError_t launch_cheb_first(const DevLayout& L, int tile_begin, int ntiles, int out0, double gamma, int batch,
-                             bool staged, hipStream_t s);
+                             int stage, hipStream_t s);
 hipError_t launch_cheb(const DevLayout& L, int tile_begin, int ntiles, int cur, double omega, double gamma, int batch,
-                       bool staged, hipStream_t s);
+                       int stage, hipStream_t s);
 hipError_t launch_moments(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_grad(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);
 hipError_t launch_div(const DevLayout& L, int tile_begin, int ntiles, hipStream_t s);

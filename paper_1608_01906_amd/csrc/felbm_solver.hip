@@ -777,17 +777,39 @@ __device__ __forceinline__ void fused_residual_check(const DevLayout& L, int ins
 // intervening barrier).  Each thread stages at most HR halo entries, HR
 // = 2 when the layout's largest halo is at most 2 TILE, else 4 (halo <=
 // kHaloRounds * TILE; the host checks): the halo registers of the
-// 2-round form leave room for more resident blocks.
+// 2-round form leave room for more resident blocks.  Vectors are read and
+// written through buffer resources (BufVec): a thread keeps one byte
+// offset per row it stages (its own, and one per halo round), shared by
+// every population and vector.  A halo round in which a wavefront has no
+// entry is skipped by the whole wavefront; the idle lanes of a wavefront
+// that has entries load with an out-of-range offset (0, no memory access)
+// and write their LDS slot, which no row reads (sw covers the halo rounded
+// up to whole wavefronts).
+//
+// The same driver with HR = 0 is the per-wavefront form: each wavefront
+// stages its own 64 rows and its own halo (kWaveHaloRounds rounds of 64,
+// rows of sibling wavefronts included) into slots only it reads, so a pass
+// is published by a wavefront-level fence instead of a block barrier and
+// the four wavefronts of a tile run their passes independently.  LDS
+// operations of one wavefront complete in issue order; the fence keeps the
+// compiler from moving a lane's stage reads above the other lanes' writes.
 
 template <int W>
 struct LocalCols {
     int lc[W];
-    __device__ __forceinline__ void load(const DevLayout& L, int64_t R, int row) {
+    // lcol: the tile form's columns (L.lcol) or the wavefront form's (L.wlcol)
+    __device__ __forceinline__ void load(const uint16_t* lcol, int64_t R, int row) {
         lc[0] = row % TILE;  // slot 0: the row itself
 #pragma unroll
-        for (int k = 1; k < W; k++) lc[k] = L.lcol[k * R + row];
+        for (int k = 1; k < W; k++) lc[k] = gat(lcol + k * R, row);
     }
 };
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // sum_k mv[k] * stage[lc[k]]
 template <typename T, int W>
@@ -798,42 +820,63 @@ __device__ __forceinline__ T lds_row_product(const T* mv, const LocalCols<W>& l,
     return acc;
 }
 
-// Drives the passes: body.pre(g) is a per-row value the staged values of
-// row g need for every population (loaded once per tile); body.stage(j, g,
-// pre) is the staged value of population j at global row g; body.keep(j,
-// own) loads what the row keeps in registers for population j;
-// body.use(j, stage_row, own) finishes the row and returns its dot-product
-// term.  sh holds 2 CH stage rows.
+// Drives the passes: body.pre(o) is a per-row value the staged values of
+// the row at byte offset o need for every population (loaded once per
+// tile); body.stage(j, o, pre) is the staged value of population j at that
+// row; body.keep(j, own) loads what the row keeps in registers for
+// population j; body.use(j, stage_row, own) finishes the row and returns
+// its dot-product term.  sh holds 2 CH stage rows (sw values each, or
+// kWaveStageWidth in the wavefront form, HR = 0).
 template <typename T, int NP, int CH, int HR, class Body>
 __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int tile, int row, T* sh,
                                            TileReducer<NP>* red) {
-    static_assert(HR >= 1 && HR <= kHaloRounds, "halo rounds out of range");
+    static_assert(HR >= 0 && HR <= kHaloRounds, "halo rounds out of range");
     static_assert(NP % CH == 0 && NP % RG == 0, "population passes must tile NP");
-    const int sw = L.sw;
-    const int hb = L.halo_ptr[tile], hn = L.halo_ptr[tile + 1] - hb;
+    constexpr bool kWave = HR == 0;
+    constexpr int NR = kWave ? kWaveHaloRounds : HR;  // halo rounds per thread
+    constexpr int RS = kWave ? 64 : TILE;             // halo entries per round
+    const int sw = kWave ? kWaveStageWidth : L.sw;
     const int lr = threadIdx.x;
-    int hg[HR];
-    T pre_h[HR];
-#pragma unroll
-    for (int i = 0; i < HR; i++) {
-        const int h = lr + i * TILE;
-        hg[i] = h < hn ? L.halo_col[hb + h] : -1;
-        pre_h[i] = hg[i] >= 0 ? body.pre(hg[i]) : T(0);
+    const int wb = __builtin_amdgcn_readfirstlane(lr) & ~63;  // the wavefront's first thread
+    // halo list; hl: this thread's entry in round 0; hs: its LDS slot in round 0
+    int hb, hn, hl, hs;
+    if constexpr (kWave) {
+        const int wv = tile * (TILE / 64) + wb / 64;
+        hb = L.whalo_ptr[wv];
+        hn = L.whalo_ptr[wv + 1] - hb;
+        hl = lr - wb;
+        hs = TILE + (wb / 64) * NR * 64 + hl;
+    } else {
+        hb = L.halo_ptr[tile];
+        hn = L.halo_ptr[tile + 1] - hb;
+        hl = lr;
+        hs = TILE + lr;
     }
-    const T pre_own = body.pre(row);
+    const int32_t* hcol = kWave ? L.whalo_col : L.halo_col;
+    bool act[NR];
+    uint32_t ho[NR];
+    T pre_h[NR];
+#pragma unroll
+    for (int i = 0; i < NR; i++) {
+        const int h = hl + i * RS;
+        act[i] = hn > i * RS + (kWave ? 0 : wb);  // uniform over the wavefront
+        ho[i] = h < hn ? (uint32_t)hcol[hb + h] * (uint32_t)sizeof(T) : kIdleRow;
+        pre_h[i] = act[i] ? body.pre(ho[i]) : T(0);
+    }
+    const T pre_own = body.pre(body.ro);
     typename Body::Own own[2][CH];
-    T v[CH], vh[HR][CH];
+    T v[CH], vh[NR][CH];
     auto fetch = [&](int j0, typename Body::Own* o) {
 #pragma unroll
         for (int u = 0; u < CH; u++) {
             body.keep(j0 + u, o[u]);
-            v[u] = body.stage(j0 + u, row, pre_own);
+            v[u] = body.stage(j0 + u, body.ro, pre_own);
         }
 #pragma unroll
-        for (int i = 0; i < HR; i++) {
-            if (hg[i] >= 0) {
+        for (int i = 0; i < NR; i++) {
+            if (act[i]) {
 #pragma unroll
-                for (int u = 0; u < CH; u++) vh[i][u] = body.stage(j0 + u, hg[i], pre_h[i]);
+                for (int u = 0; u < CH; u++) vh[i][u] = body.stage(j0 + u, ho[i], pre_h[i]);
             }
         }
     };
@@ -846,13 +889,16 @@ __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int t
 #pragma unroll
         for (int u = 0; u < CH; u++) buf[u * sw + lr] = v[u];
 #pragma unroll
-        for (int i = 0; i < HR; i++) {
-            if (hg[i] >= 0) {
+        for (int i = 0; i < NR; i++) {
+            if (act[i]) {
 #pragma unroll
-                for (int u = 0; u < CH; u++) buf[u * sw + TILE + i * TILE + lr] = vh[i][u];
+                for (int u = 0; u < CH; u++) buf[u * sw + hs + i * RS] = vh[i][u];
             }
         }
-        __syncthreads();
+        if constexpr (kWave)
+            wave_lds_sync();
+        else
+            __syncthreads();
         if (j0 + CH < NP) fetch(j0 + CH, own[p ^ 1]);
 #pragma unroll
         for (int u = 0; u < CH; u++) {
@@ -866,54 +912,54 @@ __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int t
     }
 }
 
+// Row state of every staged body: local columns, mass values, the row's
+// byte offset ro and the byte size sR of one population's slice.
+template <typename T, int W>
+struct StagedRow {
+    LocalCols<W> l;
+    T mv[W];
+    uint32_t ro, sR;
+    __device__ __forceinline__ uint32_t so(int j) const { return (uint32_t)j * sR; }
+};
+
 // cg_init staged: stage rhs / m
 template <typename T, int W>
-struct CgInitStaged {
+struct CgInitStaged : StagedRow<T, W> {
     static constexpr bool kDots = true;
     struct Own { T rhs; };
-    LocalCols<W> l;
-    T mv[W], mrow;
-    const T *rhs, *minv;
-    T* Rv;
-    int64_t R;
-    int row;
-    __device__ __forceinline__ T pre(int g) const { return minv[g]; }
-    __device__ __forceinline__ T stage(int j, int g, T mg) const { return rhs[(int64_t)j * R + g] * mg; }
-    __device__ __forceinline__ void keep(int j, Own& o) const { o.rhs = rhs[(int64_t)j * R + row]; }
-    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
-        const T acc = lds_row_product<T, W>(mv, l, st);
-        const T res = o.rhs - acc;
-        const int64_t i = (int64_t)j * R + row;
-        Rv[i] = z_form<W>() ? res * mrow : res;
+    T mrow;
+    BufVec<T> rhs, minv, rv;
+    __device__ __forceinline__ T pre(uint32_t o) const { return minv.load(o, 0); }
+    __device__ __forceinline__ T stage(int j, uint32_t o, T mg) const { return rhs.load(o, this->so(j)) * mg; }
+    __device__ __forceinline__ void keep(int j, Own& w) const { w.rhs = rhs.load(this->ro, this->so(j)); }
+    __device__ __forceinline__ double use(int j, const T* st, const Own& w) const {
+        const T acc = lds_row_product<T, W>(this->mv, this->l, st);
+        const T res = w.rhs - acc;
+        rv.store(z_form<W>() ? res * mrow : res, this->ro, this->so(j));
         return (double)res * (double)res * (double)mrow;
     }
 };
 
 // cg_a staged: stage p_new = r / m + beta p_old
 template <typename T, int W, bool FIRST>
-struct CgAStaged {
+struct CgAStaged : StagedRow<T, W> {
     static constexpr bool kDots = true;
     struct Own {};
-    LocalCols<W> l;
-    T mv[W];
-    const T *Rv, *Pold, *minv;
-    T* Pnew;
+    BufVec<T> rv, pold, pnew, minv;
     const double* beta;
-    int64_t R;
-    int row;
-    __device__ __forceinline__ T pre(int g) const { return minv[g]; }
-    __device__ __forceinline__ T stage(int j, int g, T mg) const {
-        const int64_t i = (int64_t)j * R + g;
+    __device__ __forceinline__ T pre(uint32_t o) const { return minv.load(o, 0); }
+    __device__ __forceinline__ T stage(int j, uint32_t o, T mg) const {
+        const T rg = rv.load(o, this->so(j));
         if constexpr (FIRST)
-            return Rv[i] * mg;
+            return rg * mg;
         else
-            return Rv[i] * mg + (T)beta[j] * Pold[i];
+            return rg * mg + (T)beta[j] * pold.load(o, this->so(j));
     }
     __device__ __forceinline__ void keep(int, Own&) const {}
     __device__ __forceinline__ double use(int j, const T* st, const Own&) const {
-        const T acc = lds_row_product<T, W>(mv, l, st);
+        const T acc = lds_row_product<T, W>(this->mv, this->l, st);
         const T pown = st[threadIdx.x];
-        Pnew[(int64_t)j * R + row] = pown;
+        pnew.store(pown, this->ro, this->so(j));
         return (double)pown * (double)acc;
     }
 };
@@ -922,123 +968,112 @@ struct CgAStaged {
 // beta q in place.  (The recurrence form's cg_b reads no
 // neighbour values and has no staged form.)
 template <typename T, int W, bool FIRST>
-struct CgAQStaged {
+struct CgAQStaged : StagedRow<T, W> {
     static constexpr bool kDots = true;
     struct Own { T p, q; };
-    LocalCols<W> l;
-    T mv[W];
-    const T *Rv, *minv, *Pold;
-    T *Pnew, *Qv;
+    BufVec<T> rv, pold, pnew, qv;
     const double* beta;
-    int64_t R;
-    int row;
-    __device__ __forceinline__ T pre(int) const { return T(0); }
-    __device__ __forceinline__ T stage(int j, int g, T) const { return Rv[(int64_t)j * R + g]; }
-    __device__ __forceinline__ void keep(int j, Own& o) const {
+    __device__ __forceinline__ T pre(uint32_t) const { return T(0); }
+    __device__ __forceinline__ T stage(int j, uint32_t o, T) const { return rv.load(o, this->so(j)); }
+    __device__ __forceinline__ void keep(int j, Own& w) const {
         if constexpr (!FIRST) {
-            const int64_t i = (int64_t)j * R + row;
-            o.p = Pold[i];
-            o.q = Qv[i];
+            w.p = pold.load(this->ro, this->so(j));
+            w.q = qv.load(this->ro, this->so(j));
         }
     }
-    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
-        T pn = st[threadIdx.x], qn = lds_row_product<T, W>(mv, l, st);
+    __device__ __forceinline__ double use(int j, const T* st, const Own& w) const {
+        T pn = st[threadIdx.x], qn = lds_row_product<T, W>(this->mv, this->l, st);
         if constexpr (!FIRST) {
             const T bet = (T)beta[j];
-            pn += bet * o.p;
-            qn += bet * o.q;
+            pn += bet * w.p;
+            qn += bet * w.q;
         }
-        const int64_t i = (int64_t)j * R + row;
-        Pnew[i] = pn;
-        Qv[i] = qn;
+        pnew.store(pn, this->ro, this->so(j));
+        qv.store(qn, this->ro, this->so(j));
         return (double)pn * (double)qn;
     }
 };
 
 // cg_b staged: stage p
 template <typename T, int W>
-struct CgBStaged {
+struct CgBStaged : StagedRow<T, W> {
     static constexpr bool kDots = true;
     struct Own { T r; };
-    LocalCols<W> l;
-    T mv[W], mrow;
-    const T* Pn;
-    T* Rv;
+    T mrow;
+    BufVec<T> pn, rv;
     const double* alpha;
-    int64_t R;
-    int row;
-    __device__ __forceinline__ T pre(int) const { return T(0); }
-    __device__ __forceinline__ T stage(int j, int g, T) const { return Pn[(int64_t)j * R + g]; }
-    __device__ __forceinline__ void keep(int j, Own& o) const { o.r = Rv[(int64_t)j * R + row]; }
-    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
-        const T qq = lds_row_product<T, W>(mv, l, st);
+    __device__ __forceinline__ T pre(uint32_t) const { return T(0); }
+    __device__ __forceinline__ T stage(int j, uint32_t o, T) const { return pn.load(o, this->so(j)); }
+    __device__ __forceinline__ void keep(int j, Own& w) const { w.r = rv.load(this->ro, this->so(j)); }
+    __device__ __forceinline__ double use(int j, const T* st, const Own& w) const {
+        const T qq = lds_row_product<T, W>(this->mv, this->l, st);
         const T al = (T)alpha[j];
-        const int64_t i = (int64_t)j * R + row;
-        const T res = o.r - al * qq;
-        Rv[i] = res;
+        const T res = w.r - al * qq;
+        rv.store(res, this->ro, this->so(j));
         return (double)res * (double)res * (double)mrow;
     }
 };
 
 // Chebyshev first iterate staged: stage rhs / m
 template <typename T, int W>
-struct ChebFirstStaged {
+struct ChebFirstStaged : StagedRow<T, W> {
     static constexpr bool kDots = false;
     struct Own { T rhs; };
-    LocalCols<W> l;
-    T mv[W], mrow;
-    const T *rhs, *minv;
-    T *x0, *x1;
+    T mrow;
+    BufVec<T> rhs, minv, x0, x1;
     T gamma;
-    int64_t R;
-    int row;
-    __device__ __forceinline__ T pre(int g) const { return minv[g]; }
-    __device__ __forceinline__ T stage(int j, int g, T mg) const { return rhs[(int64_t)j * R + g] * mg; }
-    __device__ __forceinline__ void keep(int j, Own& o) const { o.rhs = rhs[(int64_t)j * R + row]; }
-    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
-        const T acc = lds_row_product<T, W>(mv, l, st);
-        const T xa = o.rhs * mrow;
-        const int64_t i = (int64_t)j * R + row;
-        x0[i] = xa;
-        x1[i] = xa + gamma * ((o.rhs - acc) * mrow);
+    __device__ __forceinline__ T pre(uint32_t o) const { return minv.load(o, 0); }
+    __device__ __forceinline__ T stage(int j, uint32_t o, T mg) const { return rhs.load(o, this->so(j)) * mg; }
+    __device__ __forceinline__ void keep(int j, Own& w) const { w.rhs = rhs.load(this->ro, this->so(j)); }
+    __device__ __forceinline__ double use(int j, const T* st, const Own& w) const {
+        const T acc = lds_row_product<T, W>(this->mv, this->l, st);
+        const T xa = w.rhs * mrow;
+        x0.store(xa, this->ro, this->so(j));
+        x1.store(xa + gamma * ((w.rhs - acc) * mrow), this->ro, this->so(j));
         return 0.0;
     }
 };
 
 // Chebyshev iterate staged: stage x_k
 template <typename T, int W>
-struct ChebStaged {
+struct ChebStaged : StagedRow<T, W> {
     static constexpr bool kDots = false;
     struct Own { T b, xp; };
-    LocalCols<W> l;
-    T mv[W], mrow;
-    const T *rhs, *xk;
-    T* xp;
+    T mrow;
+    BufVec<T> rhs, xk, xp;
     T omega, gamma;
-    int64_t R;
-    int row;
-    __device__ __forceinline__ T pre(int) const { return T(0); }
-    __device__ __forceinline__ T stage(int j, int g, T) const { return xk[(int64_t)j * R + g]; }
-    __device__ __forceinline__ void keep(int j, Own& o) const {
-        const int64_t i = (int64_t)j * R + row;
-        o.b = rhs[i];
-        o.xp = xp[i];
+    __device__ __forceinline__ T pre(uint32_t) const { return T(0); }
+    __device__ __forceinline__ T stage(int j, uint32_t o, T) const { return xk.load(o, this->so(j)); }
+    __device__ __forceinline__ void keep(int j, Own& w) const {
+        w.b = rhs.load(this->ro, this->so(j));
+        w.xp = xp.load(this->ro, this->so(j));
     }
-    __device__ __forceinline__ double use(int j, const T* st, const Own& o) const {
-        const T acc = lds_row_product<T, W>(mv, l, st);
-        const T z = (o.b - acc) * mrow;
-        xp[(int64_t)j * R + row] = omega * (gamma * z + st[threadIdx.x] - o.xp) + o.xp;
+    __device__ __forceinline__ double use(int j, const T* st, const Own& w) const {
+        const T acc = lds_row_product<T, W>(this->mv, this->l, st);
+        const T z = (w.b - acc) * mrow;
+        xp.store(omega * (gamma * z + st[threadIdx.x] - w.xp) + w.xp, this->ro, this->so(j));
         return 0.0;
     }
 };
 
-template <typename T, int W, class B>
+template <typename T, int W, int HR, class B>
 __device__ __forceinline__ void staged_row_setup(B& b, const DevLayout& L, int64_t R, int row) {
-    b.l.load(L, R, row);
+    b.l.load(HR == 0 ? L.wlcol : L.lcol, R, row);
 #pragma unroll
-    for (int k = 0; k < W; k++) b.mv[k] = ld<T>(L.Mval, k * R + row);
-    b.R = R;
-    b.row = row;
+    for (int k = 0; k < W; k++) b.mv[k] = gat(reinterpret_cast<const T*>(L.Mval) + k * R, row);
+    b.ro = (uint32_t)row * (uint32_t)sizeof(T);
+    b.sR = (uint32_t)R * (uint32_t)sizeof(T);
+}
+
+// bytes of a [NP][R] vector of T (the host keeps it below 4 GiB for the
+// staged forms) and of the [R] inverse masses
+template <typename T, int NP>
+__device__ __forceinline__ uint32_t vec_bytes(const DevLayout& L) {
+    return (uint32_t)NP * (uint32_t)L.R * (uint32_t)sizeof(T);
+}
+template <typename T>
+__device__ __forceinline__ uint32_t row_bytes(const DevLayout& L) {
+    return (uint32_t)L.R * (uint32_t)sizeof(T);
 }
 
 template <typename T, int W, int NP, int CH, int HR>
@@ -1046,36 +1081,46 @@ __global__ __launch_bounds__(TILE) void k_cg_init_lds(DevLayout L, int tile_begi
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
     CgInitStaged<T, W> b;
-    staged_row_setup<T, W>(b, L, R, row);
-    b.minv = reinterpret_cast<const T*>(L.minv);
-    b.mrow = b.minv[row];
-    b.rhs = vec<T>(L.Pb);
-    b.Rv = vec<T>(L.Rv);
+    staged_row_setup<T, W, HR>(b, L, R, row);
+    const uint32_t vb = vec_bytes<T, NP>(L);
+    b.minv.bind(reinterpret_cast<const T*>(L.minv), row_bytes<T>(L));
+    b.mrow = ld<T>(L.minv, row);
+    b.rhs.bind(vec<T>(L.Pb), vb);
+    b.rv.bind(vec<T>(L.Rv), vb);
     FEL_REDUCER(red, NP);
     run_staged<T, NP, CH, HR>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
     red.finish(L, tile);
 }
 
+// Waves per SIMD the staged cg_a is held to: the FP32 2-D batch-4 form (2
+// halo rounds) fits 4 (128 registers) without spilling, where left alone
+// it takes 133 registers and runs 3 (measured on the 6.6 M-node ensemble:
+// 355 us per launch against about 420); others as the compiler allocates.
+template <typename T, int W, int CH, int HR>
+constexpr int cg_a_min_waves() {
+    return (sizeof(T) == 4 && W == 7 && CH == 4 && HR == 2) ? 4 : 1;
+}
 template <typename T, int W, int NP, int CH, int HR>
-__global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, int first, int it) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, TILE), amdgpu_waves_per_eu(cg_a_min_waves<T, W, CH, HR>())))
+void k_cg_a_lds(DevLayout L, int tile_begin, int first, int it) {
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
     const int inst = L.tile_inst[tile];
     T* sh = reinterpret_cast<T*>(fel_smem);
     FEL_REDUCER(red, NP);
+    const uint32_t vb = vec_bytes<T, NP>(L);
     auto setup = [&](auto& b) {
-        staged_row_setup<T, W>(b, L, R, row);
-        b.minv = reinterpret_cast<const T*>(L.minv);
-        b.Rv = vec<T>(L.Rv);
-        b.Pold = ph<T, NP>(L, it > 0 ? it - 1 : 0);  // unread on the first iteration
-        b.Pnew = ph<T, NP>(L, it);
+        staged_row_setup<T, W, HR>(b, L, R, row);
+        b.rv.bind(vec<T>(L.Rv), vb);
+        b.pold.bind(ph<T, NP>(L, it > 0 ? it - 1 : 0), vb);  // unread on the first iteration
+        b.pnew.bind(ph<T, NP>(L, it), vb);
         b.beta = L.beta + inst * NP;
     };
-    auto setup_q = [&](auto& b) {
-        setup(b);
-        b.Qv = vec<T>(L.Pa);
-    };
     if constexpr (q_recurrence<W>()) {
+        auto setup_q = [&](auto& b) {
+            setup(b);
+            b.qv.bind(vec<T>(L.Pa), vb);
+        };
         if (first) {
             CgAQStaged<T, W, true> b;
             setup_q(b);
@@ -1085,14 +1130,20 @@ __global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, 
             setup_q(b);
             run_staged<T, NP, CH, HR>(b, L, tile, row, sh, &red);
         }
-    } else if (first) {
-        CgAStaged<T, W, true> b;
-        setup(b);
-        run_staged<T, NP, CH, HR>(b, L, tile, row, sh, &red);
     } else {
-        CgAStaged<T, W, false> b;
-        setup(b);
-        run_staged<T, NP, CH, HR>(b, L, tile, row, sh, &red);
+        auto setup_m = [&](auto& b) {
+            setup(b);
+            b.minv.bind(reinterpret_cast<const T*>(L.minv), row_bytes<T>(L));
+        };
+        if (first) {
+            CgAStaged<T, W, true> b;
+            setup_m(b);
+            run_staged<T, NP, CH, HR>(b, L, tile, row, sh, &red);
+        } else {
+            CgAStaged<T, W, false> b;
+            setup_m(b);
+            run_staged<T, NP, CH, HR>(b, L, tile, row, sh, &red);
+        }
     }
     red.finish(L, tile);
 }
@@ -1116,10 +1167,11 @@ __global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, 
         run_rows<NP, CH>(b, &red);
     } else {
         CgBStaged<T, W> b;
-        staged_row_setup<T, W>(b, L, R, row);
+        staged_row_setup<T, W, HR>(b, L, R, row);
+        const uint32_t vb = vec_bytes<T, NP>(L);
         b.mrow = ld<T>(L.minv, row);
-        b.Pn = ph<T, NP>(L, it);
-        b.Rv = vec<T>(L.Rv);
+        b.pn.bind(ph<T, NP>(L, it), vb);
+        b.rv.bind(vec<T>(L.Rv), vb);
         b.alpha = alpha_of<NP>(L, it, inst);
         run_staged<T, NP, CH, HR>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
     }
@@ -1132,12 +1184,13 @@ __global__ __launch_bounds__(TILE) void k_cheb_first_lds(DevLayout L, int tile_b
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
     ChebFirstStaged<T, W> b;
-    staged_row_setup<T, W>(b, L, R, row);
-    b.minv = reinterpret_cast<const T*>(L.minv);
-    b.mrow = b.minv[row];
-    b.rhs = vec<T>(L.Pb);
-    b.x0 = cheb_buf<T>(L, out0);
-    b.x1 = cheb_buf<T>(L, 1 - out0);
+    staged_row_setup<T, W, HR>(b, L, R, row);
+    const uint32_t vb = vec_bytes<T, NP>(L);
+    b.minv.bind(reinterpret_cast<const T*>(L.minv), row_bytes<T>(L));
+    b.mrow = ld<T>(L.minv, row);
+    b.rhs.bind(vec<T>(L.Pb), vb);
+    b.x0.bind(cheb_buf<T>(L, out0), vb);
+    b.x1.bind(cheb_buf<T>(L, 1 - out0), vb);
     b.gamma = (T)gamma_d;
     run_staged<T, NP, CH, HR>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), (TileReducer<NP>*)nullptr);
 }
@@ -1148,11 +1201,12 @@ __global__ __launch_bounds__(TILE) void k_cheb_lds(DevLayout L, int tile_begin, 
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
     ChebStaged<T, W> b;
-    staged_row_setup<T, W>(b, L, R, row);
+    staged_row_setup<T, W, HR>(b, L, R, row);
+    const uint32_t vb = vec_bytes<T, NP>(L);
     b.mrow = ld<T>(L.minv, row);
-    b.rhs = vec<T>(L.Pb);
-    b.xk = cheb_buf<T>(L, cur);
-    b.xp = cheb_buf<T>(L, 1 - cur);
+    b.rhs.bind(vec<T>(L.Pb), vb);
+    b.xk.bind(cheb_buf<T>(L, cur), vb);
+    b.xp.bind(cheb_buf<T>(L, 1 - cur), vb);
     b.omega = (T)omega_d;
     b.gamma = (T)gamma_d;
     run_staged<T, NP, CH, HR>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), (TileReducer<NP>*)nullptr);
@@ -1176,11 +1230,11 @@ __global__ __launch_bounds__(TILE) void k_lumped(DevLayout L, int tile_begin) {
 constexpr size_t kMaxStageBytes = kStageBytes;  // plus the static reducer buffer
 
 // halo rounds of the staged instantiation a layout runs (its stage row is
-// TILE plus the largest halo, rounded up to 32)
+// TILE plus the largest halo, rounded up to 64)
 inline int staged_halo_rounds(const DevLayout& L) { return L.sw - TILE <= 2 * TILE ? 2 : 4; }
 
-// Launches kernel K<T, W, NP, CH> (or, when staged, K_lds with 2 ch sw
-// values of dynamic LDS) for the context's value type and the population
+// Launches kernel K<T, W, NP, CH> (or, when staged, K_lds with 2 ch stage
+// rows of dynamic LDS) for the context's value type and the population
 // batch ch (1, 2 or 4).
 #define FEL_SOLVER_LAUNCH_T(K, T, SH, ch, s, nt, ...)                                    \
     do {                                                                               \
@@ -1193,56 +1247,65 @@ inline int staged_halo_rounds(const DevLayout& L) { return L.sw - TILE <= 2 * TI
 
 // The staged kernels' halo registers are sized for HR rounds of TILE
 // entries: 2 when the layout's largest halo fits (smaller register
-// footprint, more resident blocks), else 4.
-#define FEL_STAGED_LAUNCH_T(K, T, SH, ch, hr, s, nt, ...)                                         \
-    do {                                                                                          \
-        switch (ch) {                                                                             \
-        case 4:                                                                                   \
-            if (hr == 2) FEL_LAUNCH((K<T, W, NP, 4, 2>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); \
-            else FEL_LAUNCH((K<T, W, NP, 4, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);         \
-            break;                                                                                \
-        case 2:                                                                                   \
-            if (hr == 2) FEL_LAUNCH((K<T, W, NP, 2, 2>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); \
-            else FEL_LAUNCH((K<T, W, NP, 2, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);         \
-            break;                                                                                \
-        default:                                                                                  \
-            if (hr == 2) FEL_LAUNCH((K<T, W, NP, 1, 2>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); \
-            else FEL_LAUNCH((K<T, W, NP, 1, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);         \
-        }                                                                                         \
+// footprint, more resident blocks), else 4; HR = 0 is the per-wavefront
+// form (kWaveHaloRounds rounds of 64 entries), built for ELL width 7.
+#define FEL_STAGED_LAUNCH_HR(K, T, SH, C, hr, s, nt, ...)                                          \
+    do {                                                                                           \
+        if (hr == 0) {                                                                             \
+            if constexpr (W == 7) FEL_LAUNCH((K<T, W, NP, C, 0>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); \
+            else return hipErrorInvalidValue;                                                      \
+        } else if (hr == 2) {                                                                      \
+            FEL_LAUNCH((K<T, W, NP, C, 2>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);              \
+        } else {                                                                                   \
+            FEL_LAUNCH((K<T, W, NP, C, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);              \
+        }                                                                                          \
+    } while (0)
+#define FEL_STAGED_LAUNCH_T(K, T, SH, ch, hr, s, nt, ...)                  \
+    do {                                                                   \
+        switch (ch) {                                                      \
+        case 4: FEL_STAGED_LAUNCH_HR(K, T, SH, 4, hr, s, nt, __VA_ARGS__); break; \
+        case 2: FEL_STAGED_LAUNCH_HR(K, T, SH, 2, hr, s, nt, __VA_ARGS__); break; \
+        default: FEL_STAGED_LAUNCH_HR(K, T, SH, 1, hr, s, nt, __VA_ARGS__);       \
+        }                                                                  \
     } while (0)
 
-#define FEL_SOLVER_LAUNCH(K, ch, staged, s, nt, ...)                                   \
+// stage: 1 direct, 2 per tile, 3 per wavefront
+#define FEL_SOLVER_LAUNCH(K, ch, stage, s, nt, ...)                                   \
     do {                                                                              \
         const bool f64_ = L.precision == 0;                                           \
-        if (staged) {                                                                 \
-            const size_t sh_ = 2 * (size_t)(ch) * L.sw * (f64_ ? 8 : 4);              \
-            if (sh_ > kMaxStageBytes || L.sw > TILE + kHaloRounds * TILE)             \
+        if (stage == 2 || stage == 3) {                                               \
+            const bool wave_ = stage == 3;                                            \
+            const size_t sh_ = 2 * (size_t)(ch) * (wave_ ? kWaveStageWidth : L.sw) * (f64_ ? 8 : 4); \
+            if (sh_ > kMaxStageBytes || L.sw > TILE + kHaloRounds * TILE ||          \
+                !staged_vectors_fit(NP, L.R, L.precision) || (wave_ && !L.wlcol))     \
                 return hipErrorInvalidValue;                                          \
-            const int hr_ = staged_halo_rounds(L);                                    \
+            const int hr_ = wave_ ? 0 : staged_halo_rounds(L);                        \
             if (f64_) FEL_STAGED_LAUNCH_T(K##_lds, double, sh_, ch, hr_, s, nt, __VA_ARGS__); \
             else FEL_STAGED_LAUNCH_T(K##_lds, float, sh_, ch, hr_, s, nt, __VA_ARGS__);       \
-        } else {                                                                      \
+        } else if (stage == 1) {                                                      \
             if (f64_) FEL_SOLVER_LAUNCH_T(K, double, 0, ch, s, nt, __VA_ARGS__);          \
             else FEL_SOLVER_LAUNCH_T(K, float, 0, ch, s, nt, __VA_ARGS__);                \
+        } else {                                                                      \
+            return hipErrorInvalidValue;                                              \
         }                                                                             \
     } while (0)
 
 template <int Q, int W> struct CgInitBody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, int ch, bool st, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int ch, int st, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         FEL_SOLVER_LAUNCH(k_cg_init, ch, st, s, nt, L, tb);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct CgABody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, bool first, int it, int ch, bool st, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, bool first, int it, int ch, int st, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         FEL_SOLVER_LAUNCH(k_cg_a, ch, st, s, nt, L, tb, (int)first, it);
         FEL_CHECK_LAUNCH();
     }
 };
 template <int Q, int W> struct CgBBody {
-    static hipError_t run(const DevLayout& L, int tb, int nt, int it, int ch, bool st, hipStream_t s) {
+    static hipError_t run(const DevLayout& L, int tb, int nt, int it, int ch, int st, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         FEL_SOLVER_LAUNCH(k_cg_b, ch, st, s, nt, L, tb, it);
         FEL_CHECK_LAUNCH();
@@ -1250,7 +1313,7 @@ template <int Q, int W> struct CgBBody {
 };
 template <int Q, int W> struct ChebFirstBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, int out0, double gamma, int ch,
-                          bool st, hipStream_t s) {
+                          int st, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         FEL_SOLVER_LAUNCH(k_cheb_first, ch, st, s, nt, L, tb, out0, gamma);
         FEL_CHECK_LAUNCH();
@@ -1258,7 +1321,7 @@ template <int Q, int W> struct ChebFirstBody {
 };
 template <int Q, int W> struct ChebBody {
     static hipError_t run(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma,
-                          int ch, bool st, hipStream_t s) {
+                          int ch, int st, hipStream_t s) {
         constexpr int NP = 2 * (Q - 1);
         FEL_SOLVER_LAUNCH(k_cheb, ch, st, s, nt, L, tb, cur, omega, gamma);
         FEL_CHECK_LAUNCH();
@@ -1275,18 +1338,17 @@ template <int Q, int W> struct LumpedBody {
     }
 };
 
-hipError_t launch_cg_init(const DevLayout& L, int tb, int nt, int batch, bool staged,
-                          hipStream_t s) {
-    return dispatch_qw<CgInitBody>(L, tb, nt, batch, staged, s);
+hipError_t launch_cg_init(const DevLayout& L, int tb, int nt, int batch, int stage, hipStream_t s) {
+    return dispatch_qw<CgInitBody>(L, tb, nt, batch, stage, s);
 }
-hipError_t launch_cg_a(const DevLayout& L, int tb, int nt, bool first, int it, int batch, bool staged,
+hipError_t launch_cg_a(const DevLayout& L, int tb, int nt, bool first, int it, int batch, int stage,
                        hipStream_t s) {
     if (it < 0 || it >= L.K || (!first && it == 0)) return hipErrorInvalidValue;
-    return dispatch_qw<CgABody>(L, tb, nt, first, it, batch, staged, s);
+    return dispatch_qw<CgABody>(L, tb, nt, first, it, batch, stage, s);
 }
-hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, int it, int batch, bool staged, hipStream_t s) {
+hipError_t launch_cg_b(const DevLayout& L, int tb, int nt, int it, int batch, int stage, hipStream_t s) {
     if (it < 0 || it >= L.K) return hipErrorInvalidValue;
-    return dispatch_qw<CgBBody>(L, tb, nt, it, batch, staged, s);
+    return dispatch_qw<CgBBody>(L, tb, nt, it, batch, stage, s);
 }
 hipError_t launch_cg_x(const DevLayout& L, int tb, int nt, bool check, hipStream_t s) {
     (void)hipGetLastError();
@@ -1306,12 +1368,12 @@ hipError_t launch_cg_x(const DevLayout& L, int tb, int nt, bool check, hipStream
     return hipGetLastError();
 }
 hipError_t launch_cheb_first(const DevLayout& L, int tb, int nt, int out0, double gamma, int batch,
-                             bool staged, hipStream_t s) {
-    return dispatch_qw<ChebFirstBody>(L, tb, nt, out0, gamma, batch, staged, s);
+                             int stage, hipStream_t s) {
+    return dispatch_qw<ChebFirstBody>(L, tb, nt, out0, gamma, batch, stage, s);
 }
 hipError_t launch_cheb(const DevLayout& L, int tb, int nt, int cur, double omega, double gamma,
-                       int batch, bool staged, hipStream_t s) {
-    return dispatch_qw<ChebBody>(L, tb, nt, cur, omega, gamma, batch, staged, s);
+                       int batch, int stage, hipStream_t s) {
+    return dispatch_qw<ChebBody>(L, tb, nt, cur, omega, gamma, batch, stage, s);
 }
 hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {
     return dispatch_qw<LumpedBody>(L, tb, nt, s);

@@ -24,7 +24,7 @@ AUX = {"gradrho": 0, "mu": 1, "S": 2, "delta": 3}
 ABI_SYMBOLS = ["fel_create", "fel_upload_mesh", "fel_workspace_size", "fel_bind", "fel_bind_static", "fel_init_fields",
                "fel_step", "fel_sync", "fel_read_fields", "fel_conserved_sums", "fel_get_state",
                "fel_set_state", "fel_read_aux", "fel_profile", "fel_profile_read", "fel_layout_info",
-               "fel_tuning", "fel_destroy", "fel_last_error", "fel_version"]
+               "fel_stage_tables", "fel_tuning", "fel_destroy", "fel_last_error", "fel_version"]
 
 
 class FelOptions(C.Structure):
@@ -83,6 +83,7 @@ def load_library():
                                      C.POINTER(C.c_char_p)]
     lib.fel_layout_info.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                     C.POINTER(C.c_int), C.POINTER(C.c_int), _dp]
+    lib.fel_stage_tables.argtypes = [_vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64), _vp, _vp, _vp]
     lib.fel_tuning.argtypes = [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int)]
     lib.fel_destroy.argtypes = [_vp]
@@ -249,10 +250,24 @@ class Context:
         return dict(rows=rows.value, ell_width=w.value, pops=pops.value, cg_iters=it.value, halo_max=hmax.value,
                     halo_mean=hmean.value)
 
+    def stage_tables(self, form: int):
+        """LDS staging tables of the layout before binding (form 2 per tile,
+        3 per wavefront): lcol [ell_width][rows] uint16, list_ptr, list_col."""
+        nl, nc = C.c_int64(0), C.c_int64(0)
+        self._check(self.lib.fel_stage_tables(self.h, form, C.byref(nl), C.byref(nc), None, None, None),
+                    "fel_stage_tables")
+        info = self.layout_info()
+        lcol = np.zeros((info["ell_width"], info["rows"]), np.uint16)
+        ptr = np.zeros(nl.value + 1, np.int32)
+        col = np.zeros(max(nc.value, 1), np.int32)
+        self._check(self.lib.fel_stage_tables(self.h, form, C.byref(nl), C.byref(nc), lcol.ctypes.data,
+                                              ptr.ctypes.data, col.ctypes.data), "fel_stage_tables")
+        return dict(lcol=lcol, list_ptr=ptr, list_col=col[:nc.value])
+
     def tuning(self):
         """Schedule in use, keyed by kernel class name: (population batch,
-        staging: 1 direct gathers, 2 LDS-staged); under "fused" the CG
-        reduction form (1 finalize launches, 2 fused)."""
+        staging: 1 direct gathers, 2 LDS-staged per tile, 3 per wavefront);
+        under "fused" the CG reduction form (1 finalize launches, 2 fused)."""
         n, fused = C.c_int(0), C.c_int(0)
         batch, staging = (C.c_int * 32)(), (C.c_int * 32)()
         self._check(self.lib.fel_tuning(self.h, 32, C.byref(n), batch, staging, C.byref(fused)), "fel_tuning")

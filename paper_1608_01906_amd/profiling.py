@@ -79,20 +79,24 @@ def short_name(name: str) -> str:
 
 def staged_halo_rounds(halo_max: int, tile: int = 256) -> int:
     """Halo rounds of the staged instantiation a layout runs: its stage row
-    holds the tile and the largest halo rounded up to 32; 2 rounds when the
+    holds the tile and the largest halo rounded up to 64; 2 rounds when the
     halo part fits in 2 tiles, else 4."""
-    sw = (tile + halo_max + 31) // 32 * 32
+    sw = (tile + halo_max + 63) // 64 * 64
     return 2 if sw - tile <= 2 * tile else 4
 
 
-def solver_kernel_name(cls: str, precision: str, W: int, NP: int, batch: int, staged: bool,
+def solver_kernel_name(cls: str, precision: str, W: int, NP: int, batch: int, staged,
                        fused: bool = False, halo_max: int = 0) -> str:
     """Short name of the solver kernel a schedule launches (cheb: the
-    iterate kernel, which runs all but the first of each solve); staged
-    kernels carry the halo rounds of the layout (largest halo halo_max)."""
+    iterate kernel, which runs all but the first of each solve).  staged:
+    False direct, True a stage per tile (the kernel carries the halo rounds
+    of the layout, largest halo halo_max), "wave" a stage per wavefront
+    (halo rounds 0)."""
     T = "double" if precision == "fp64" else "float"
     if fused and cls in ("cg_init", "cg_a", "cg_b"):
         return f"fel::k_{cls}_fused<{T}, {W}, {NP}, {batch}>"
+    if staged == "wave":
+        return f"fel::k_{cls}_lds<{T}, {W}, {NP}, {batch}, 0>"
     if staged:
         return f"fel::k_{cls}_lds<{T}, {W}, {NP}, {batch}, {staged_halo_rounds(halo_max)}>"
     return f"fel::k_{cls}<{T}, {W}, {NP}, {batch}>"

@@ -38,24 +38,26 @@ def test_bad_options_rejected():
     for nb in (3, 8, -1):
         with pytest.raises(felbm.FelError):
             felbm.Context(9, solver_batch=nb)
-    for sg in (3, -1):
+    for sg in (4, -1):
         with pytest.raises(felbm.FelError):
             felbm.Context(9, lds_staging=sg)
+    for fr in (3, -1):
         with pytest.raises(felbm.FelError):
-            felbm.Context(9, fused_reductions=sg)
+            felbm.Context(9, fused_reductions=fr)
 
 
 def test_tuning_before_bind():
     """A fixed solver schedule shows on the solver kernels at once; 0 (timed
     at the first step) reads 0 until then; the streaming kernel (batch 1)
-    takes the staging option too, which binding settles to direct where it
-    has no staged form; other kernels read (1, 1)."""
+    takes the staging option too (its staged form is per tile, so 3 reads
+    2), which binding settles to direct where it has no staged form; other
+    kernels read (1, 1)."""
     solver = ("cg_init", "cg_a", "cg_b", "cheb")
     for nb in (0, 1, 2, 4):
-        for sg in (0, 1, 2):
+        for sg in (0, 1, 2, 3):
             t = felbm.Context(19, solver_batch=nb, lds_staging=sg).tuning()
             assert all(t[k] == (nb, sg) for k in solver)
-            assert t["stream"] == (1, sg)
+            assert t["stream"] == (1, min(sg, 2))
             assert all(v == (1, 1) for k, v in t.items() if k not in solver and k not in ("stream", "fused"))
             assert t["fused"] == 0
 

@@ -97,6 +97,9 @@ def test_solver_kernel_name():
         "fel::k_cg_b_lds<float, 7, 16, 4, 2>"
     assert profiling.solver_kernel_name("cg_b", "fp32", 7, 16, 4, True, halo_max=516) == \
         "fel::k_cg_b_lds<float, 7, 16, 4, 4>"
+    # the per-wavefront stage: halo rounds 0 whatever the tile halos
+    assert profiling.solver_kernel_name("cg_a", "fp32", 7, 16, 2, "wave", halo_max=266) == \
+        "fel::k_cg_a_lds<float, 7, 16, 2, 0>"
     assert profiling.solver_kernel_name("cg_a", "fp32", 7, 16, 4, False) == "fel::k_cg_a<float, 7, 16, 4>"
     # the Chebyshev kernels have no fused form
     assert profiling.solver_kernel_name("cheb", "fp32", 7, 16, 2, False, True) == "fel::k_cheb<float, 7, 16, 2>"

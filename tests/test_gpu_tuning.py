@@ -3,9 +3,13 @@
 The batch only sets how far ahead a solver kernel issues its loads (or how
 many populations an LDS pass stages); every population's row sum and its
 tile reduction run in the same order, so all batches of one form give
-bitwise equal states.  The staged form reads the same neighbour values from
-LDS instead of memory; it agrees with the direct form to rounding (the two
-may contract multiply-adds differently) and is checked against the oracle.
+bitwise equal states.  The staged forms (a stage per tile, a stage per
+64-row wavefront) read the same neighbour values from LDS instead of
+memory; they agree with the direct form to rounding (the forms may contract
+multiply-adds differently) and are checked against the oracle.  The
+per-wavefront form exists for ELL width 7 (the 2-D grids): forced on a 3-D
+layout, or with a batch whose stage does not fit 60 KB of LDS (FP64, batch
+4), the first step reports FEL_EINVAL.
 """
 import numpy as np
 import pytest
@@ -47,24 +51,30 @@ def test_solver_schedules(felbm, oracle_mod, dim, precision, mass_mode, node_ord
     tol = 1e-11 if precision == "fp64" else 2e-5
     used = ("cheb",) if mass_mode == 2 else ("cg_init", "cg_a", "cg_b")
     states = {}
-    for sg in (1, 2):
+    for sg in (1, 2, 3):
         for nb in (1, 2, 4):
             print("case", dim, precision, mass_mode, node_order, sg, nb, flush=True)
             ctx = felbm.from_workload(w, precision=precision, mass_mode=mass_mode, solver_batch=nb,
                                       lds_staging=sg, node_order=node_order, fused_reductions=1)
+            if sg == 3 and (dim == 3 or (precision == "fp64" and nb == 4)):
+                with pytest.raises(felbm.FelError) as ei:
+                    ctx.step(steps)
+                assert ei.value.status == felbm.FEL_EINVAL
+                continue
             ctx.step(steps)
             ctx.sync()
             states[sg, nb] = ctx.get_state(0)
             t = ctx.tuning()
             # on 3-D layouts the second CG kernel reads no neighbour values: never staged
             assert all(t[name] == (nb, 1 if (name == "cg_b" and dim == 3) else sg) for name in SOLVER)
-            # the streaming kernel has a staged form for 2-D deviation storage
-            assert t["stream"] == (1, sg if (dim == 2 and precision != "fp64") else 1), t["stream"]
+            # the streaming kernel has a staged form (per tile) for 2-D deviation storage
+            assert t["stream"] == (1, min(sg, 2) if (dim == 2 and precision != "fp64") else 1), t["stream"]
             e = compare_fields(ctx.read_fields(0), o.fields(), inst)
             for k in ("rho", "u", "C"):
                 assert e[k] < tol, (sg, nb, k, e[k])
         for nb in (2, 4):
-            np.testing.assert_array_equal(states[sg, 1], states[sg, nb])
+            if (sg, nb) in states:
+                np.testing.assert_array_equal(states[sg, 1], states[sg, nb])
     # the tuner's choice is one of the candidates, for the kernels in use
     ctx = felbm.from_workload(w, precision=precision, mass_mode=mass_mode, node_order=node_order)
     ctx.step(steps)
@@ -72,7 +82,7 @@ def test_solver_schedules(felbm, oracle_mod, dim, precision, mass_mode, node_ord
     t = ctx.tuning()
     for name in SOLVER:
         b, sg = t[name]
-        assert (b in (1, 2, 4) and sg in (1, 2)) if name in used else (b, sg) == (1, 1), (name, t[name])
+        assert (b in (1, 2, 4) and sg in (1, 2, 3)) if name in used else (b, sg) == (1, 1), (name, t[name])
     e = compare_fields(ctx.read_fields(0), o.fields(), inst)
     for k in ("rho", "u", "C"):
         assert e[k] < tol, ("tuned", k, e[k])
@@ -89,7 +99,7 @@ def test_tuning_reads_zero_before_first_step(felbm):
     t = ctx.tuning()
     assert t["cheb"] == (1, 1) and t["fused"] in (1, 2)
     assert t["stream"] in ((1, 1), (1, 2))
-    assert all(t[k][0] in (1, 2, 4) and t[k][1] in (1, 2) for k in ("cg_init", "cg_a", "cg_b"))
+    assert all(t[k][0] in (1, 2, 4) and t[k][1] in (1, 2, 3) for k in ("cg_init", "cg_a", "cg_b"))
 
 
 @pytest.mark.parametrize("node_order", [0, 1])
@@ -110,19 +120,20 @@ def test_staged_stream_fp16_storage_vs_oracle(felbm, oracle_mod, node_order):
     tol = fp16_storage_bound(max(d0, max_deviation(o.get_state(), ref, w.lattice)), inst.phys.rho_l,
                              inst.phys.rho_v, steps)
     got = {}
-    for sg in (1, 2):
+    for sg in (1, 2, 3):
         ctx = felbm.from_workload(w, precision="fp32_fp16", lds_staging=sg, node_order=node_order,
                                   fused_reductions=1)
         ctx.step(steps)
         ctx.sync()
-        assert ctx.tuning()["stream"] == (1, sg)
+        assert ctx.tuning()["stream"] == (1, min(sg, 2))
         got[sg] = ctx.read_fields(0)
         e = compare_fields(got[sg], ref, inst)
         print("fp16 storage, staging", sg, {k: f"{v:.2e}" for k, v in e.items()}, "bound", f"{tol:.2e}", flush=True)
         for k in ("rho", "C"):
             assert e[k] < tol, (sg, k, e[k], tol)
-    e = compare_fields(got[2], got[1], inst)
-    assert e["rho"] < 1e-5 and e["C"] < 1e-4, e
+    for sg in (2, 3):
+        e = compare_fields(got[sg], got[1], inst)
+        assert e["rho"] < 1e-5 and e["C"] < 1e-4, (sg, e)
 
 
 @pytest.mark.parametrize("mass_mode", [0, 2])
@@ -133,7 +144,7 @@ def test_partly_fixed_schedules_are_kept(felbm, mass_mode):
     launches forced, so the choice applies to the kernels that run)."""
     w = _workload(2)
     classes = ("cg_init", "cg_a", "cg_b") if mass_mode == 0 else ("cheb",)
-    for sg in (1, 2):
+    for sg in (1, 2, 3):
         ctx = felbm.from_workload(w, precision="fp32", mass_mode=mass_mode, lds_staging=sg, fused_reductions=1)
         ctx.step(1)
         ctx.sync()
@@ -146,7 +157,7 @@ def test_partly_fixed_schedules_are_kept(felbm, mass_mode):
         ctx.sync()
         t = ctx.tuning()
         print("batch fixed", b, t, flush=True)
-        assert all(t[k][0] == b and t[k][1] in (1, 2) for k in classes)
+        assert all(t[k][0] == b and t[k][1] in (1, 2, 3) for k in classes)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
