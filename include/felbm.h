@@ -103,7 +103,9 @@ typedef struct {
                              the populations whose neighbour loads it issues ahead of use (its
                              software-pipeline depth), with LDS staging the populations staged per
                              pass; 1, 2 or 4 for every solver kernel, or 0 = chosen per kernel by
-                             timing on the bound layout before the first step */
+                             timing on the bound layout before the first step.  FP64 layouts of ELL
+                             width 12 and up run the direct kernels at batch 2 at most (4 would spill
+                             registers): a fixed 4 with direct gathers runs and reads back as 2 */
     int lds_staging;      /* mass-solve kernels read neighbour values 1 = by direct gathers from
                              memory, 2 = from a per-tile stage in LDS (the tile's rows and its halo
                              loaded once per population, coalesced; a block barrier per pass),
@@ -126,8 +128,8 @@ typedef struct {
     int fused_reductions; /* consistent-mass CG: 1 = a finalize launch forms each CG scalar from the
                              tile partials (two per iteration); 2 = fused: 1024-thread blocks leave
                              at most 256 partials per instance and every block of the next launch
-                             sums them itself (D2Q9 layouts with instances of at most 1024 tiles,
-                             else fel_bind returns FEL_EINVAL); 0 = chosen by timing both solves on
+                             sums them itself (D2Q9 layouts of ELL width 7 with instances of at most
+                             1024 tiles, else fel_bind returns FEL_EINVAL); 0 = chosen by timing both solves on
                              the bound layout before the first step (1 where fused is unavailable).
                              Same results to rounding (the partial sums group rows differently).
                              The fused kernels' 1024-thread blocks leave 128 registers per thread,

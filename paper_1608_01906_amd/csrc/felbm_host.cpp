@@ -622,11 +622,11 @@ static void build_wave_halos(fel_ctx* c) {
 // kFusedTiles (the last group may be short), listed in dispatch order so
 // that, with block b running on XCD b % 8, each XCD receives a contiguous
 // range of blocks (as tile_of_block does for the one-tile blocks).  The
-// path is available for D2Q9 layouts whose instances have at most
-// kFusedMaxBlocks blocks.
+// path is available for D2Q9 layouts of ELL width 7 whose instances have at
+// most kFusedMaxBlocks blocks.
 static void build_fused_blocks(fel_ctx* c) {
     std::vector<int32_t> order;
-    c->fused_ok = c->opt.lattice == 9 && (c->W == 7 || c->W == 12);
+    c->fused_ok = c->opt.lattice == 9 && c->W == 7;
     for (int i = 0; i < c->ninst; i++) {
         InstParams& P = c->inst[i].P;
         const int nb = (P.tile_count + kFusedTiles - 1) / kFusedTiles;
@@ -664,6 +664,9 @@ static fel_status plan_layout(fel_ctx* c) {
     c->W = supported_width(c->opt.lattice, wmax);
     if (c->W < 0) return fail(c, FEL_EINVAL, "mesh valence %d above the supported ELL width", wmax);
     if (c->W >= kQRecurrenceWidth) c->stage[KC_CG_B] = 1;  // recurrence form: cg_b has no staged form
+    // a fixed direct schedule runs at the largest batch built for it
+    for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B, KC_CHEB})
+        if (c->stage[k] == 1) c->batch[k] = std::min(c->batch[k], direct_max_batch(c->W, (int)elem_size(c->opt.precision)));
     int64_t rows = 0;
     c->tile_inst.clear();
     for (int i = 0; i < n; i++) {
@@ -901,7 +904,7 @@ static fel_status bind_range(fel_ctx* c, void* dev_ptr, size_t bytes, void* hip_
     c->dev = static_cast<char*>(dev_ptr);
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (c->fused == 2 && !c->fused_ok && c->opt.mass_mode == FEL_MASS_CONSISTENT)
-        return fail(c, FEL_EINVAL, "fused reductions need a D2Q9 layout (ELL width 7 or 12) with at most %d "
+        return fail(c, FEL_EINVAL, "fused reductions need a D2Q9 layout of ELL width 7 with at most %d "
                     "blocks of %d tiles per instance", kFusedMaxBlocks, kFusedTiles);
     set_pointers(c);
     st = upload_operators(c);
@@ -971,7 +974,7 @@ fel_status fel::bind_static_workspace(fel_ctx* c, void* ptr, size_t bytes, void*
     if (st != FEL_OK) return st;
     if (c->fused == 2)
         for (int k : {KC_CG_INIT, KC_CG_A, KC_CG_B})
-            c->fbatch[k] = c->W == 7 ? std::min(c->batch[k], fused_max_batch(k, c->opt.precision)) : 1;
+            c->fbatch[k] = std::min(c->batch[k], fused_max_batch(k, c->opt.precision));
     c->use_graph = false;
     c->static_dev = device;
     std::lock_guard<std::mutex> lk(g_static_mu);
@@ -1165,6 +1168,7 @@ fel_status tune_schedule(fel_ctx* c) {
             for (int t : {1, 2, 4}) {
                 if (c->batch[cls] != 0 && c->batch[cls] != t) continue;
                 if (sg >= 2 && !stage_fits(c, t, sg)) continue;
+                if (sg == 1 && t > direct_max_batch(c->W, (int)elem_size(c->opt.precision))) continue;
                 (void)hipGetLastError();
                 hipError_t e = hipSuccess;
                 for (int r = 0; r < kWarm && e == hipSuccess; r++) e = run(cls, t, sg);
@@ -1200,7 +1204,7 @@ fel_status tune_schedule(fel_ctx* c) {
     return st;
 }
 
-// Population batches of the fused kernels (1, 2, 4; width 12 only 1), by
+// Population batches of the fused kernels (1, 2, 4), by
 // timing, unless solver_batch fixes them.
 fel_status tune_fused_batches(fel_ctx* c) {
     const DevLayout& L = c->L;
@@ -1209,7 +1213,7 @@ fel_status tune_fused_batches(fel_ctx* c) {
     const int prec = c->opt.precision;
     if (c->opt.solver_batch) {
         for (int cls : {KC_CG_INIT, KC_CG_A, KC_CG_B})
-            c->fbatch[cls] = c->W == 7 ? std::min(c->opt.solver_batch, fused_max_batch(cls, prec)) : 1;
+            c->fbatch[cls] = std::min(c->opt.solver_batch, fused_max_batch(cls, prec));
         return FEL_OK;
     }
     hipEvent_t a = get_event(c), b = get_event(c);
@@ -1219,7 +1223,7 @@ fel_status tune_fused_batches(fel_ctx* c) {
         int best = 0;
         float best_ms = 0.0f;
         for (int t : {1, 2, 4}) {
-            if ((c->W != 7 && t != 1) || t > fused_max_batch(cls, prec)) continue;
+            if (t > fused_max_batch(cls, prec)) continue;
             float ms = 0.0f;
             hipError_t e = time_launches(c, a, b, [&] {
                 return cls == KC_CG_INIT ? launch_cg_init_fused(L, t, s)
@@ -1340,7 +1344,8 @@ fel_status refine_schedule(fel_ctx* c) {
             if (!fused && fixed_st && st != fixed_st) continue;
             for (int t : {1, 2, 4}) {
                 if (sb && t != sb) continue;
-                if (fused && ((c->W != 7 && t != 1) || t > fused_max_batch(cls, c->opt.precision))) continue;
+                if (fused && t > fused_max_batch(cls, c->opt.precision)) continue;
+                if (!fused && st == 1 && t > direct_max_batch(c->W, (int)elem_size(c->opt.precision))) continue;
                 if (st >= 2 && !stage_fits(c, t, st)) continue;
                 if (t == keep_b && st == keep_s) continue;
                 *bt = t;

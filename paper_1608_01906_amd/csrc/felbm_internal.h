@@ -161,6 +161,11 @@ int fused_max_batch(int cls, int precision);
 // 3-D layouts, where neighbour gathers dominate): the second CG kernel then
 // reads own rows only and has no staged form.
 constexpr int kQRecurrenceWidth = 15;
+// Largest population batch of the direct solver kernels: in FP64 at ELL
+// width 12 and up the double-buffered gathers of a batch of 4 would spill
+// registers, so those layouts stop at 2 (a fixed batch of 4 runs, and
+// reads back from fel_tuning, as 2).
+constexpr int direct_max_batch(int W, int elem_bytes) { return elem_bytes == 8 && W >= 12 ? 2 : 4; }
 constexpr int kHaloRounds = 4;       // LDS staging: halo entries per thread at most (halo <= 4 TILE)
 // LDS staging per wavefront: halo entries per lane at most (a wavefront's
 // halo <= 192), and the stage row: the tile's rows, then 3 x 64 halo slots

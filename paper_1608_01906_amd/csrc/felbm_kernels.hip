@@ -41,7 +41,10 @@ __global__ __launch_bounds__(TILE) void k_stream_plain(DevLayout L, int tile_beg
     double acc[NP];
 #pragma unroll
     for (int j = 0; j < NP; j++) acc[j] = 0.0;
-#pragma unroll
+    // one slot at a time: the accumulators and a slot's 2(Q-1) gathers fill
+    // the registers (unrolling the slots too ran one wave per SIMD in 2-D
+    // and spilled in 3-D)
+#pragma unroll 1
     for (int k = 0; k < W; k++) {
         const int64_t c = ell_col(L, k, row);
         double b[NB];

@@ -99,18 +99,20 @@ struct NoHook {
 
 // `before_use` runs once the loads of the first two batches are issued,
 // before any population is used (the fused kernels form their CG scalars
-// there, so that latency overlaps the loads).
-template <int NP, int CH, class Body, class Red, class Hook = NoHook>
+// there, so that latency overlaps the loads).  PIPE = false loads each
+// batch only after the previous one is used (one register set instead of
+// two, for kernels that would spill otherwise).
+template <int NP, int CH, bool PIPE = true, class Body, class Red, class Hook = NoHook>
 __device__ __forceinline__ void run_rows(Body& body, Red* red, Hook before_use = Hook()) {
     static_assert(NP % CH == 0 && NP % RG == 0, "population batches must tile NP");
-    typename Body::Regs buf[2][CH];
+    typename Body::Regs buf[PIPE ? 2 : 1][CH];
 #pragma unroll
     for (int u = 0; u < CH; u++) body.load(u, buf[0][u]);
     double dots[RG];
 #pragma unroll
     for (int j0 = 0; j0 < NP; j0 += CH) {
-        const int cur = (j0 / CH) & 1;
-        if (j0 + CH < NP) {
+        const int cur = PIPE ? (j0 / CH) & 1 : 0;
+        if (PIPE && j0 + CH < NP) {
 #pragma unroll
             for (int u = 0; u < CH; u++) body.load(j0 + CH + u, buf[cur ^ 1][u]);
         }
@@ -123,6 +125,10 @@ __device__ __forceinline__ void run_rows(Body& body, Red* red, Hook before_use =
                 dots[j % RG] = d;
                 if (j % RG == RG - 1) red->add_group(j - (RG - 1), dots);
             }
+        }
+        if (!PIPE && j0 + CH < NP) {
+#pragma unroll
+            for (int u = 0; u < CH; u++) body.load(j0 + CH + u, buf[0][u]);
         }
     }
 }
@@ -701,16 +707,19 @@ __global__ __launch_bounds__(FB_THREADS) void k_cg_a_fused(DevLayout L, int it) 
     const T* Rv = vec<T>(L.Rv);
     const T* Pold = ph<T, NP>(L, it > 0 ? it - 1 : 0);  // unread on the first iteration
     T* Pnew = ph<T, NP>(L, it);
+    // FP64: the two population register sets of the pipeline would spill
+    // under the 128 registers of a 1024-thread block
+    constexpr bool pipe = sizeof(T) == 4;
     if (it == 0) {
         CgARows<T, W, true> b;
         b.o.load(L, R, row);
         b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.beta = bet, b.R = R, b.row = row, b.live = active;
-        run_rows<NP, CH>(b, &red, scalars);
+        run_rows<NP, CH, pipe>(b, &red, scalars);
     } else {
         CgARows<T, W, false> b;
         b.o.load(L, R, row);
         b.Rv = Rv, b.Pold = Pold, b.Pnew = Pnew, b.beta = bet, b.R = R, b.row = row, b.live = active;
-        run_rows<NP, CH>(b, &red, scalars);
+        run_rows<NP, CH, pipe>(b, &red, scalars);
     }
     red.finish_to(L.fpart1, L.nfb, pidx, FB_WAVES);
 }
@@ -1239,7 +1248,12 @@ inline int staged_halo_rounds(const DevLayout& L) { return L.sw - TILE <= 2 * TI
 #define FEL_SOLVER_LAUNCH_T(K, T, SH, ch, s, nt, ...)                                    \
     do {                                                                               \
         switch (ch) {                                                                  \
-        case 4: FEL_LAUNCH((K<T, W, NP, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); break; \
+        case 4:                                                                        \
+            if constexpr (direct_max_batch(W, sizeof(T)) >= 4)                         \
+                FEL_LAUNCH((K<T, W, NP, 4>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); \
+            else                                                                       \
+                return hipErrorInvalidValue;                                           \
+            break;                                                                     \
         case 2: FEL_LAUNCH((K<T, W, NP, 2>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__); break; \
         default: FEL_LAUNCH((K<T, W, NP, 1>), dim3(nt), dim3(TILE), SH, s, __VA_ARGS__);       \
         }                                                                              \
@@ -1379,11 +1393,12 @@ hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {
     return dispatch_qw<LumpedBody>(L, tb, nt, s);
 }
 
-// Fused kernels: 2-D only (the host enables the path for D2Q9 layouts).
-// Their 1024-thread blocks cap a thread at 128 VGPRs, so only the
-// population batches that fit without spilling are built (fused_max_batch:
-// cg_init 4 in FP32 / 2 in FP64, cg_a 1, cg_b 4 / 1); a larger batch runs
-// as the largest built one.
+// Fused kernels: D2Q9 layouts of ELL width 7 only (the host enables the
+// path there; at width 12 their rows would spill registers).  Their
+// 1024-thread blocks cap a thread at 128 VGPRs, so only the population
+// batches that fit without spilling are built (fused_max_batch: cg_init 4
+// in FP32 / 2 in FP64, cg_a 1, cg_b 4 / 1); a larger batch runs as the
+// largest built one.
 #define FEL_FUSED_W7(K, T, B, s, ...) FEL_LAUNCH((K<T, 7, 16, B>), g_, b_, 0, s, __VA_ARGS__)
 #define FEL_FUSED_LAUNCH(K, ch, MAX32, MAX64, s, ...)                                                 \
     do {                                                                                              \
@@ -1401,9 +1416,6 @@ hipError_t launch_lumped(const DevLayout& L, int tb, int nt, hipStream_t s) {
                 else if (MAX32 >= 2 && c_ == 2) FEL_FUSED_W7(K, float, (MAX32 >= 2 ? 2 : 1), s, __VA_ARGS__); \
                 else FEL_FUSED_W7(K, float, 1, s, __VA_ARGS__);                                       \
             }                                                                                         \
-        } else if (L.W == 12) {                                                                       \
-            if (f64_) FEL_LAUNCH((K<double, 12, 16, 1>), g_, b_, 0, s, __VA_ARGS__);                   \
-            else FEL_LAUNCH((K<float, 12, 16, 1>), g_, b_, 0, s, __VA_ARGS__);                         \
         } else {                                                                                      \
             return hipErrorInvalidValue;                                                              \
         }                                                                                             \

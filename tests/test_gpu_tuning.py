@@ -65,8 +65,12 @@ def test_solver_schedules(felbm, oracle_mod, dim, precision, mass_mode, node_ord
             ctx.sync()
             states[sg, nb] = ctx.get_state(0)
             t = ctx.tuning()
-            # on 3-D layouts the second CG kernel reads no neighbour values: never staged
-            assert all(t[name] == (nb, 1 if (name == "cg_b" and dim == 3) else sg) for name in SOLVER)
+            # on 3-D layouts the second CG kernel reads no neighbour values: never staged; the
+            # direct FP64 kernels of ELL width 15 stop at batch 2
+            for name in SOLVER:
+                st = 1 if (name == "cg_b" and dim == 3) else sg
+                cap = 2 if (precision == "fp64" and dim == 3 and st == 1) else 4
+                assert t[name] == (min(nb, cap), st), (name, t[name])
             # the streaming kernel has a staged form (per tile) for 2-D deviation storage
             assert t["stream"] == (1, min(sg, 2) if (dim == 2 and precision != "fp64") else 1), t["stream"]
             e = compare_fields(ctx.read_fields(0), o.fields(), inst)
