@@ -831,11 +831,14 @@ __device__ __forceinline__ T lds_row_product(const T* mv, const LocalCols<W>& l,
 
 // Drives the passes: body.pre(o) is a per-row value the staged values of
 // the row at byte offset o need for every population (loaded once per
-// tile); body.stage(j, o, pre) is the staged value of population j at that
-// row; body.keep(j, own) loads what the row keeps in registers for
-// population j; body.use(j, stage_row, own) finishes the row and returns
-// its dot-product term.  sh holds 2 CH stage rows (sw values each, or
-// kWaveStageWidth in the wavefront form, HR = 0).
+// tile); body.load(j, o, raw) issues the loads of population j's staged
+// value at that row and body.value(j, raw, pre) forms it, when the stage
+// is written (a pass later: forming it where the loads are issued would
+// make the wavefront wait for them there, inside the halo branch, before
+// it has used the current pass); body.keep(j, own) loads what the row
+// keeps in registers for population j; body.use(j, stage_row, own)
+// finishes the row and returns its dot-product term.  sh holds 2 CH stage
+// rows (sw values each, or kWaveStageWidth in the wavefront form, HR = 0).
 template <typename T, int NP, int CH, int HR, class Body>
 __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int tile, int row, T* sh,
                                            TileReducer<NP>* red) {
@@ -873,35 +876,40 @@ __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int t
         pre_h[i] = act[i] ? body.pre(ho[i]) : T(0);
     }
     const T pre_own = body.pre(body.ro);
+    // The tile's own rows (coalesced, most of the bytes) are loaded two
+    // passes ahead, the halo (mostly L2 hits) and the kept values one.
     typename Body::Own own[2][CH];
-    T v[CH], vh[NR][CH];
+    typename Body::Raw v[2][CH], vh[NR][CH];
+    auto fetch_own = [&](int j0, typename Body::Raw* dst) {
+#pragma unroll
+        for (int u = 0; u < CH; u++) body.load(j0 + u, body.ro, dst[u]);
+    };
     auto fetch = [&](int j0, typename Body::Own* o) {
 #pragma unroll
-        for (int u = 0; u < CH; u++) {
-            body.keep(j0 + u, o[u]);
-            v[u] = body.stage(j0 + u, body.ro, pre_own);
-        }
+        for (int u = 0; u < CH; u++) body.keep(j0 + u, o[u]);
 #pragma unroll
         for (int i = 0; i < NR; i++) {
             if (act[i]) {
 #pragma unroll
-                for (int u = 0; u < CH; u++) vh[i][u] = body.stage(j0 + u, ho[i], pre_h[i]);
+                for (int u = 0; u < CH; u++) body.load(j0 + u, ho[i], vh[i][u]);
             }
         }
     };
+    fetch_own(0, v[0]);
     fetch(0, own[0]);
+    if (CH < NP) fetch_own(CH, v[1]);
     double dots[RG];
 #pragma unroll
     for (int j0 = 0; j0 < NP; j0 += CH) {
         const int p = (j0 / CH) & 1;
         T* buf = sh + p * CH * sw;
 #pragma unroll
-        for (int u = 0; u < CH; u++) buf[u * sw + lr] = v[u];
+        for (int u = 0; u < CH; u++) buf[u * sw + lr] = body.value(j0 + u, v[p][u], pre_own);
 #pragma unroll
         for (int i = 0; i < NR; i++) {
             if (act[i]) {
 #pragma unroll
-                for (int u = 0; u < CH; u++) buf[u * sw + hs + i * RS] = vh[i][u];
+                for (int u = 0; u < CH; u++) buf[u * sw + hs + i * RS] = body.value(j0 + u, vh[i][u], pre_h[i]);
             }
         }
         if constexpr (kWave)
@@ -909,6 +917,7 @@ __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int t
         else
             __syncthreads();
         if (j0 + CH < NP) fetch(j0 + CH, own[p ^ 1]);
+        if (j0 + 2 * CH < NP) fetch_own(j0 + 2 * CH, v[p]);
 #pragma unroll
         for (int u = 0; u < CH; u++) {
             const int j = j0 + u;
@@ -918,6 +927,9 @@ __device__ __forceinline__ void run_staged(Body& body, const DevLayout& L, int t
                 if (j % RG == RG - 1) red->add_group(j - (RG - 1), dots);
             }
         }
+        // keep the next pass's staged values from being formed (and their
+        // loads waited for) ahead of this pass's rows
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -936,10 +948,12 @@ template <typename T, int W>
 struct CgInitStaged : StagedRow<T, W> {
     static constexpr bool kDots = true;
     struct Own { T rhs; };
+    struct Raw { T v; };
     T mrow;
     BufVec<T> rhs, minv, rv;
     __device__ __forceinline__ T pre(uint32_t o) const { return minv.load(o, 0); }
-    __device__ __forceinline__ T stage(int j, uint32_t o, T mg) const { return rhs.load(o, this->so(j)) * mg; }
+    __device__ __forceinline__ void load(int j, uint32_t o, Raw& w) const { w.v = rhs.load(o, this->so(j)); }
+    __device__ __forceinline__ T value(int, const Raw& w, T mg) const { return w.v * mg; }
     __device__ __forceinline__ void keep(int j, Own& w) const { w.rhs = rhs.load(this->ro, this->so(j)); }
     __device__ __forceinline__ double use(int j, const T* st, const Own& w) const {
         const T acc = lds_row_product<T, W>(this->mv, this->l, st);
@@ -954,15 +968,19 @@ template <typename T, int W, bool FIRST>
 struct CgAStaged : StagedRow<T, W> {
     static constexpr bool kDots = true;
     struct Own {};
+    struct Raw { T r, p; };
     BufVec<T> rv, pold, pnew, minv;
-    const double* beta;
+    const T* beta;  // LDS copy
     __device__ __forceinline__ T pre(uint32_t o) const { return minv.load(o, 0); }
-    __device__ __forceinline__ T stage(int j, uint32_t o, T mg) const {
-        const T rg = rv.load(o, this->so(j));
+    __device__ __forceinline__ void load(int j, uint32_t o, Raw& w) const {
+        w.r = rv.load(o, this->so(j));
+        if constexpr (!FIRST) w.p = pold.load(o, this->so(j));
+    }
+    __device__ __forceinline__ T value(int j, const Raw& w, T mg) const {
         if constexpr (FIRST)
-            return rg * mg;
+            return w.r * mg;
         else
-            return rg * mg + (T)beta[j] * pold.load(o, this->so(j));
+            return w.r * mg + beta[j] * w.p;
     }
     __device__ __forceinline__ void keep(int, Own&) const {}
     __device__ __forceinline__ double use(int j, const T* st, const Own&) const {
@@ -980,10 +998,12 @@ template <typename T, int W, bool FIRST>
 struct CgAQStaged : StagedRow<T, W> {
     static constexpr bool kDots = true;
     struct Own { T p, q; };
+    struct Raw { T v; };
     BufVec<T> rv, pold, pnew, qv;
-    const double* beta;
+    const T* beta;  // LDS copy
     __device__ __forceinline__ T pre(uint32_t) const { return T(0); }
-    __device__ __forceinline__ T stage(int j, uint32_t o, T) const { return rv.load(o, this->so(j)); }
+    __device__ __forceinline__ void load(int j, uint32_t o, Raw& w) const { w.v = rv.load(o, this->so(j)); }
+    __device__ __forceinline__ T value(int, const Raw& w, T) const { return w.v; }
     __device__ __forceinline__ void keep(int j, Own& w) const {
         if constexpr (!FIRST) {
             w.p = pold.load(this->ro, this->so(j));
@@ -993,7 +1013,7 @@ struct CgAQStaged : StagedRow<T, W> {
     __device__ __forceinline__ double use(int j, const T* st, const Own& w) const {
         T pn = st[threadIdx.x], qn = lds_row_product<T, W>(this->mv, this->l, st);
         if constexpr (!FIRST) {
-            const T bet = (T)beta[j];
+            const T bet = beta[j];
             pn += bet * w.p;
             qn += bet * w.q;
         }
@@ -1008,15 +1028,17 @@ template <typename T, int W>
 struct CgBStaged : StagedRow<T, W> {
     static constexpr bool kDots = true;
     struct Own { T r; };
+    struct Raw { T v; };
     T mrow;
     BufVec<T> pn, rv;
-    const double* alpha;
+    const T* alpha;  // LDS copy
     __device__ __forceinline__ T pre(uint32_t) const { return T(0); }
-    __device__ __forceinline__ T stage(int j, uint32_t o, T) const { return pn.load(o, this->so(j)); }
+    __device__ __forceinline__ void load(int j, uint32_t o, Raw& w) const { w.v = pn.load(o, this->so(j)); }
+    __device__ __forceinline__ T value(int, const Raw& w, T) const { return w.v; }
     __device__ __forceinline__ void keep(int j, Own& w) const { w.r = rv.load(this->ro, this->so(j)); }
     __device__ __forceinline__ double use(int j, const T* st, const Own& w) const {
         const T qq = lds_row_product<T, W>(this->mv, this->l, st);
-        const T al = (T)alpha[j];
+        const T al = alpha[j];
         const T res = w.r - al * qq;
         rv.store(res, this->ro, this->so(j));
         return (double)res * (double)res * (double)mrow;
@@ -1028,11 +1050,13 @@ template <typename T, int W>
 struct ChebFirstStaged : StagedRow<T, W> {
     static constexpr bool kDots = false;
     struct Own { T rhs; };
+    struct Raw { T v; };
     T mrow;
     BufVec<T> rhs, minv, x0, x1;
     T gamma;
     __device__ __forceinline__ T pre(uint32_t o) const { return minv.load(o, 0); }
-    __device__ __forceinline__ T stage(int j, uint32_t o, T mg) const { return rhs.load(o, this->so(j)) * mg; }
+    __device__ __forceinline__ void load(int j, uint32_t o, Raw& w) const { w.v = rhs.load(o, this->so(j)); }
+    __device__ __forceinline__ T value(int, const Raw& w, T mg) const { return w.v * mg; }
     __device__ __forceinline__ void keep(int j, Own& w) const { w.rhs = rhs.load(this->ro, this->so(j)); }
     __device__ __forceinline__ double use(int j, const T* st, const Own& w) const {
         const T acc = lds_row_product<T, W>(this->mv, this->l, st);
@@ -1048,11 +1072,13 @@ template <typename T, int W>
 struct ChebStaged : StagedRow<T, W> {
     static constexpr bool kDots = false;
     struct Own { T b, xp; };
+    struct Raw { T v; };
     T mrow;
     BufVec<T> rhs, xk, xp;
     T omega, gamma;
     __device__ __forceinline__ T pre(uint32_t) const { return T(0); }
-    __device__ __forceinline__ T stage(int j, uint32_t o, T) const { return xk.load(o, this->so(j)); }
+    __device__ __forceinline__ void load(int j, uint32_t o, Raw& w) const { w.v = xk.load(o, this->so(j)); }
+    __device__ __forceinline__ T value(int, const Raw& w, T) const { return w.v; }
     __device__ __forceinline__ void keep(int j, Own& w) const {
         w.b = rhs.load(this->ro, this->so(j));
         w.xp = xp.load(this->ro, this->so(j));
@@ -1107,7 +1133,7 @@ __global__ __launch_bounds__(TILE) void k_cg_init_lds(DevLayout L, int tile_begi
 // 355 us per launch against about 420); others as the compiler allocates.
 template <typename T, int W, int CH, int HR>
 constexpr int cg_a_min_waves() {
-    return (sizeof(T) == 4 && W == 7 && CH == 4 && HR == 2) ? 4 : 1;
+    return (sizeof(T) == 4 && W == 7 && CH == 4 && HR == 2) ? 1 : 1;
 }
 template <typename T, int W, int NP, int CH, int HR>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, TILE), amdgpu_waves_per_eu(cg_a_min_waves<T, W, CH, HR>())))
@@ -1117,13 +1143,17 @@ void k_cg_a_lds(DevLayout L, int tile_begin, int first, int it) {
     const int inst = L.tile_inst[tile];
     T* sh = reinterpret_cast<T*>(fel_smem);
     FEL_REDUCER(red, NP);
+    // beta of the instance in LDS: read where the staged values are formed
+    __shared__ T sbeta[NP];
+    if (threadIdx.x < NP) sbeta[threadIdx.x] = (T)L.beta[inst * NP + threadIdx.x];
+    __syncthreads();
     const uint32_t vb = vec_bytes<T, NP>(L);
     auto setup = [&](auto& b) {
         staged_row_setup<T, W, HR>(b, L, R, row);
         b.rv.bind(vec<T>(L.Rv), vb);
         b.pold.bind(ph<T, NP>(L, it > 0 ? it - 1 : 0), vb);  // unread on the first iteration
         b.pnew.bind(ph<T, NP>(L, it), vb);
-        b.beta = L.beta + inst * NP;
+        b.beta = sbeta;
     };
     if constexpr (q_recurrence<W>()) {
         auto setup_q = [&](auto& b) {
@@ -1175,13 +1205,17 @@ __global__ __launch_bounds__(TILE) void k_cg_b_lds(DevLayout L, int tile_begin, 
         b.row = row;
         run_rows<NP, CH>(b, &red);
     } else {
+        // alpha of the instance in LDS
+        __shared__ T salpha[NP];
+        if (threadIdx.x < NP) salpha[threadIdx.x] = (T)alpha_of<NP>(L, it, inst)[threadIdx.x];
+        __syncthreads();
         CgBStaged<T, W> b;
         staged_row_setup<T, W, HR>(b, L, R, row);
         const uint32_t vb = vec_bytes<T, NP>(L);
         b.mrow = ld<T>(L.minv, row);
         b.pn.bind(ph<T, NP>(L, it), vb);
         b.rv.bind(vec<T>(L.Rv), vb);
-        b.alpha = alpha_of<NP>(L, it, inst);
+        b.alpha = salpha;
         run_staged<T, NP, CH, HR>(b, L, tile, row, reinterpret_cast<T*>(fel_smem), &red);
     }
     red.finish(L, tile);
