@@ -244,3 +244,43 @@ def test_fused_unavailable_cases(felbm):
     ctx.step(1)
     ctx.sync()
     assert ctx.tuning()["fused"] == 1
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
+@pytest.mark.parametrize("stage", [2, 3])
+def test_staged_forms_uneven_batch_vs_oracle(felbm, oracle_mod, precision, tol, stage):
+    """Both LDS stagings (per tile, per 64-row wavefront) on three uneven
+    instances in one Z-ordered layout (sides 11, 70, 37: a single partial
+    tile, full and ragged tiles, wavefronts that straddle instance padding),
+    every population batch, against the oracle on each instance; the
+    batches of one form are bitwise equal."""
+    from paper_1608_01906_amd.inputs import Workload, droplet_instance, grid_mesh_2d
+    insts = []
+    for i, (n, ratio) in enumerate([(11, 10.0), (70, 3.0), (37, 20.0)]):
+        mesh = grid_mesh_2d(n, n, seed=900 + i)
+        insts.append(droplet_instance(mesh, radius=n / 4, rho_l=1.0, rho_v=1.0 / ratio, sigma=0.01, xi=4.0,
+                                      tau_l=0.05, tau_v=0.1, center=np.array([n / 2, n / 2])))
+    w = Workload("batch3", 9, insts, 6)
+    refs = []
+    for inst in insts:
+        o = oracle_mod.Oracle(inst.mesh, 9, inst.phys)
+        o.init(inst.rho0, inst.u0, inst.p0)
+        o.step(6)
+        refs.append(o.fields())
+    states = {}
+    for nb in (1, 2) if precision == "fp64" and stage == 3 else (1, 2, 4):
+        print("case", precision, stage, nb, flush=True)
+        ctx = felbm.from_workload(w, precision=precision, solver_batch=nb, lds_staging=stage, node_order=1,
+                                  fused_reductions=1)
+        ctx.step(6)
+        ctx.sync()
+        t = ctx.tuning()
+        assert all(t[k] == (nb, stage) for k in ("cg_init", "cg_a", "cg_b")), t
+        states[nb] = [ctx.get_state(i) for i in range(len(insts))]
+        for i, inst in enumerate(insts):
+            e = compare_fields(ctx.read_fields(i), refs[i], inst)
+            for k in ("rho", "u", "C"):
+                assert e[k] < tol, (nb, i, k, e[k])
+    for nb in states:
+        for a, b in zip(states[1], states[nb]):
+            np.testing.assert_array_equal(a, b)
