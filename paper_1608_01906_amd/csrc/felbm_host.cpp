@@ -1010,9 +1010,8 @@ hipError_t timed(fel_ctx* c, int cls, F&& launch) {
     return e;
 }
 
-// Whether a class runs its LDS-staged kernel, and whether batch ch fits the
-// staged kernel (its dynamic LDS holds 2 ch stage rows of sw values, and a
-// thread stages at most kHaloRounds halo entries).
+// Whether a class runs its LDS-staged kernel (the streaming kernel's one
+// staged form is per tile; the solver classes pass their stage on).
 bool staged(const fel_ctx* c, int cls) { return c->stage[cls] == 2; }
 // The streaming kernel's staged form: 2-D layouts of ELL width 7 in
 // deviation storage, 2 reference rows and 2 x 2 stage rows of sw floats.
@@ -1020,7 +1019,11 @@ bool stream_stage_ok(const fel_ctx* c) {
     return c->opt.lattice == 9 && c->W == 7 && c->opt.precision != 0 && c->hmax <= kHaloRounds * TILE &&
            6 * (size_t)c->sw * sizeof(float) <= (size_t)kStageBytes;
 }
-// stage 2 per tile, 3 per wavefront
+// Whether batch ch fits a solver kernel's staged form (stage 2 per tile, 3
+// per wavefront): its dynamic LDS holds 2 ch stage rows (sw values, or
+// kWaveStageWidth), a thread stages at most kHaloRounds halo entries (the
+// per-wavefront tables exist only where every wavefront halo fits), and the
+// CG vectors fit one buffer resource.
 bool stage_fits(const fel_ctx* c, int ch, int stage) {
     const size_t row = stage == 3 ? (size_t)kWaveStageWidth : (size_t)c->sw;
     return (stage == 3 ? c->wave_ok : c->hmax <= kHaloRounds * TILE) &&
