@@ -120,3 +120,27 @@ def test_stage_tables_availability():
     for bad in (0, 1, 4):
         with pytest.raises(felbm.FelError):
             ctx.stage_tables(bad)
+
+
+def test_scattered_numbering_has_no_wavefront_form():
+    """A grid whose nodes are numbered at random, kept in the caller's order:
+    a 64-row wavefront then references about 6 x 64 other rows, more than
+    its 192 halo slots, so the per-wavefront tables are not built (form 3 is
+    refused); the per-tile tables still map every slot to its column."""
+    m = grid_mesh_2d(40, 40, jitter=0.0)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(m["xyz"].shape[0])
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    shuffled = dict(m, xyz=m["xyz"][perm], conn=inv[m["conn"]].astype(m["conn"].dtype))
+    for key in ("wall", "wall_normal"):
+        if key in m:
+            shuffled[key] = m[key][perm]
+    ctx = _context([shuffled], 0)
+    with pytest.raises(felbm.FelError):
+        ctx.stage_tables(3)
+    t2 = ctx.stage_tables(2)
+    got = _columns(t2, 2, None)
+    nb = _neighbour_sets(shuffled)
+    for k in range(shuffled["xyz"].shape[0]):
+        assert set(got[:, k].tolist()) == nb[k]
