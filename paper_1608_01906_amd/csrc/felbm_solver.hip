@@ -1127,17 +1127,8 @@ __global__ __launch_bounds__(TILE) void k_cg_init_lds(DevLayout L, int tile_begi
     red.finish(L, tile);
 }
 
-// Waves per SIMD the staged cg_a is held to: the FP32 2-D batch-4 form (2
-// halo rounds) fits 4 (128 registers) without spilling, where left alone
-// it takes 133 registers and runs 3 (measured on the 6.6 M-node ensemble:
-// 355 us per launch against about 420); others as the compiler allocates.
-template <typename T, int W, int CH, int HR>
-constexpr int cg_a_min_waves() {
-    return (sizeof(T) == 4 && W == 7 && CH == 4 && HR == 2) ? 1 : 1;
-}
 template <typename T, int W, int NP, int CH, int HR>
-__global__ __attribute__((amdgpu_flat_work_group_size(1, TILE), amdgpu_waves_per_eu(cg_a_min_waves<T, W, CH, HR>())))
-void k_cg_a_lds(DevLayout L, int tile_begin, int first, int it) {
+__global__ __launch_bounds__(TILE) void k_cg_a_lds(DevLayout L, int tile_begin, int first, int it) {
     FEL_ROW_LAYOUT();
     extern __shared__ __align__(16) unsigned char fel_smem[];
     const int inst = L.tile_inst[tile];
