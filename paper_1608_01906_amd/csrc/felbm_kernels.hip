@@ -508,15 +508,19 @@ __global__ __launch_bounds__(TILE) void k_stream_dev_lds(DevLayout L, int tile_b
 #pragma unroll
         for (int n = 0; n < NB; n++) b[k][n] = __builtin_nontemporal_load(&B[((int64_t)n * W + k) * R + row]);
     }
-    float v[2], vh[HR][2];
+    // the stored values as loaded; converted when the stage is written (a
+    // conversion where the halo is loaded would wait for the loads inside
+    // the halo branch, before the current direction is used)
+    const S* ps = reinterpret_cast<const S*>(L.psi);
+    S v[2], vh[HR][2];
     auto fetch = [&](int a) {
-        v[0] = ldS<S>(L.psi, (int64_t)a * R + row);
-        v[1] = ldS<S>(L.psi, (int64_t)(Q + a) * R + row);
+        v[0] = ps[(int64_t)a * R + row];
+        v[1] = ps[(int64_t)(Q + a) * R + row];
 #pragma unroll
         for (int i = 0; i < HR; i++) {
             if (hg[i] >= 0) {
-                vh[i][0] = ldS<S>(L.psi, (int64_t)a * R + hg[i]);
-                vh[i][1] = ldS<S>(L.psi, (int64_t)(Q + a) * R + hg[i]);
+                vh[i][0] = ps[(int64_t)a * R + hg[i]];
+                vh[i][1] = ps[(int64_t)(Q + a) * R + hg[i]];
             }
         }
     };
@@ -532,13 +536,13 @@ __global__ __launch_bounds__(TILE) void k_stream_dev_lds(DevLayout L, int tile_b
 #pragma unroll
     for (int a = 1; a < Q; a++) {
         float* buf = st + ((a - 1) & 1) * 2 * sw;
-        buf[lr] = v[0];
-        buf[sw + lr] = v[1];
+        buf[lr] = (float)v[0];
+        buf[sw + lr] = (float)v[1];
 #pragma unroll
         for (int i = 0; i < HR; i++) {
             if (hg[i] >= 0) {
-                buf[TILE + i * TILE + lr] = vh[i][0];
-                buf[sw + TILE + i * TILE + lr] = vh[i][1];
+                buf[TILE + i * TILE + lr] = (float)vh[i][0];
+                buf[sw + TILE + i * TILE + lr] = (float)vh[i][1];
             }
         }
         __syncthreads();
@@ -558,6 +562,9 @@ __global__ __launch_bounds__(TILE) void k_stream_dev_lds(DevLayout L, int tile_b
         const float w = (float)LT::w(a);
         rhs[(int64_t)(a - 1) * R + row] = -w * af;
         rhs[(int64_t)(Q - 1 + a - 1) * R + row] = -w * ag;
+        // keep the next direction's conversions (and the waits for its loads)
+        // behind this direction's rows
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
